@@ -1,0 +1,186 @@
+/*
+ * helm.h -- C ABI of the MI355X three-grid IOFD Helmholtz library.
+ *
+ * The library applies the matrix-free 27-point IOFD operator with PML
+ * stretching on the h, 2h and 4h grids (Sec. 2.2, eq. iofd-shell-form,
+ * eq. pml-second-difference, Sec. 3.1), the complex-shifted 2h-4h auxiliary
+ * cycle (eq. shifted-auxiliary-cycle), restriction and prolongation
+ * (eq. full-weighting, eq. linear-prolongation), the unshifted 2h solve
+ * (eq. unshifted-middle-solve), the fine smoother and Algorithm 1, and the
+ * outer FGMRES (Sec. 3.3) to a relative residual (eq. relative-residual).
+ *
+ * Conventions (all entry points)
+ *   Grid sizes   Physical intervals nx, ny, nz; n_pml cells per face; the total
+ *                grid has N_a = n_a + 2 n_pml intervals per axis, each N_a
+ *                divisible by 4 and >= 8.  Level l in {0, 1, 2} (spacing
+ *                2^l h) has N_a / 2^l intervals and (N_a/2^l + 1) nodes.
+ *   Layout       Grid functions are [z][y][x], x fastest, all nodes including
+ *                the boundary, complex interleaved (re, im): complex128 in
+ *                HELM_FP64 mode, complex64 in HELM_FP32 mode (the "precision
+ *                vector type" below).  Nodes with an index 0 or N on any axis
+ *                are boundary nodes (u = 0, eq. helmholtz-pml): operators read
+ *                them as zero and write zero there.
+ *   Pointers     Grid functions, the velocity and the workspace are DEVICE
+ *                pointers owned by the caller; iters/relres and dot results are
+ *                HOST pointers.  The library owns only the opaque hierarchy.
+ *   Streams      All device work is enqueued on options.stream (a hipStream_t;
+ *                NULL = default stream).  Entry points that return host values
+ *                (helm_solve, helm_vec_dots, helm_setup's velocity check)
+ *                synchronise that stream; the others return without waiting.
+ *   Errors       Arguments are validated on the host before any device work;
+ *                nothing throws across the ABI.  helm_last_error() returns the
+ *                message of the last failing call (per hierarchy, or per thread
+ *                for calls that had no hierarchy).
+ *   Threads      A hierarchy must not be used by two threads at once, and two
+ *                calls on one hierarchy must not overlap on different streams
+ *                (they share the workspace).
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct helm_hierarchy helm_hierarchy;
+
+typedef enum {
+    HELM_OK = 0,
+    HELM_NOT_CONVERGED = 1, /* warning: outputs written, max_outer reached */
+    HELM_EINVAL = -1,       /* invalid argument (nothing was enqueued) */
+    HELM_EWORKSPACE = -2,   /* workspace too small or misaligned */
+    HELM_EHIP = -3,         /* a HIP runtime call failed */
+    HELM_BREAKDOWN = -4,    /* non-finite Krylov quantity (NaN/Inf in the data) */
+    HELM_ENOTIMPL = -5
+} helm_status;
+
+typedef enum { HELM_FP64 = 0, HELM_FP32 = 1 } helm_precision;
+
+/* Level operators accepted by helm_apply */
+typedef enum {
+    HELM_OP_A = 0,      /* A_l = L_l - M_l, unshifted (eq. physical-iofd-levels) */
+    HELM_OP_B = 1,      /* B_l = L_l - (1 + i sigma) M_l (eq. shifted-iofd-levels) */
+    HELM_OP_Q = 2,      /* amplitude correction Q_h, level 0 only (eq. q-operator) */
+    HELM_OP_DIAG_A = 3, /* y = diag(A_l) x */
+    HELM_OP_DIAG_B = 4  /* y = diag(B_l) x */
+} helm_op;
+
+/* Solver configuration.  helm_default_options() fills the fixed
+ * configuration of the paper's performance table: sigma 0.9; omega_h 0.8,
+ * omega_2h 0.8, omega_4h 0.2; gamma_max 1.119058; nJ_h = nJ_2h = nJ_4h = 2;
+ * m_h 2; c_2h 2; m_2h 10; m_4h 4; m_out 5. */
+typedef struct {
+    int struct_size;          /* sizeof(helm_options) */
+    helm_precision precision; /* arithmetic and vector type of the hot path */
+    double sigma, omega_h, omega_2h, omega_4h, gamma_max;
+    int nJ_h, nJ_2h, nJ_4h;   /* Jacobi sweeps per level, 1..8 */
+    int m_h, c_2h, m_2h, m_4h, m_out; /* m_h, m_2h, m_out in 1..16; m_4h in 1..8; c_2h in 1..8 */
+    int max_outer;            /* preconditioner calls per right-hand side (<= 0: 1000) */
+    const double *iofd_table; /* HOST, (K+1)*8*2 doubles: [node k][function f][value, slope],
+                                 f = alpha1..alpha5, beta1..beta3, nodes eta_k = 0.4 k / K.
+                                 Required (the paper takes these values as given data);
+                                 copied during helm_setup. */
+    int iofd_K;               /* number of table intervals, 1..128 */
+    void *stream;             /* hipStream_t */
+} helm_options;
+
+/* Fill *opt with the defaults above (table NULL, stream NULL, FP32). */
+helm_status helm_default_options(helm_options *opt);
+
+/* Bytes of device workspace helm_setup needs for this grid and options
+ * (host-only computation, no device call). */
+helm_status helm_workspace_size(int nx, int ny, int nz, int n_pml, const helm_options *opt, size_t *bytes);
+
+/* Build the operator hierarchy (Sec. 3.1): the velocity is extended into the
+ * PML by its nearest physical value (Sec. 2.1) and sampled at the nodes of
+ * each level; the per-axis PML factors (eq. pml-profile, half nodes averaged
+ * before inversion) and the table are uploaded.
+ *   velocity  DEVICE float[(nz+1)(ny+1)(nx+1)], physical nodes, m/s, finite > 0
+ *   h, omega  fine spacing (m) and angular frequency (rad/s), finite > 0
+ *   workspace DEVICE, >= helm_workspace_size() bytes, 256-byte aligned, owned by
+ *             the caller and kept alive until helm_destroy
+ * Returns HELM_EINVAL for a non-positive or non-finite velocity value. */
+helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, double omega, int n_pml,
+                       const helm_options *opt, void *workspace, size_t ws_bytes, helm_hierarchy **out);
+
+/* Solve A_h v = Q_h f and return u = Q_h v for nrhs right-hand sides
+ * (eq. iofd-complete-system) with outer FGMRES(m_out) right preconditioned by
+ * Algorithm 1, from v = 0, until ||A_h v - b|| / ||b|| <= tol recomputed with
+ * FP64 arithmetic (eq. relative-residual).
+ *   f, u    DEVICE [nrhs][total grid] precision vectors (may not alias)
+ *   iters   HOST int[nrhs]: preconditioner calls per right-hand side
+ *   relres  HOST double[nrhs]: final true relative residual
+ * Returns HELM_NOT_CONVERGED (u still written) if a right-hand side spent
+ * max_outer preconditioner calls. */
+helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, int *iters,
+                       double *relres);
+
+/* Misfit gradient with respect to squared slowness (adjoint solve through the
+ * same hierarchy).  Not available in this version: returns HELM_ENOTIMPL. */
+helm_status helm_grad(helm_hierarchy *H, const void *adj_src, int nrhs, double tol, float *grad_m);
+
+void helm_destroy(helm_hierarchy *H);
+
+/* Message of the last failing call on H (H == NULL: of this thread). */
+const char *helm_last_error(const helm_hierarchy *H);
+
+/* Total intervals (Nx, Ny, Nz) of level 0..2. */
+helm_status helm_dims(const helm_hierarchy *H, int level, int dims[3]);
+
+/* ---- Steps of the hot path (same kernels as helm_solve; used by the tests
+ *      and the benchmark).  All vectors are DEVICE precision vectors of the
+ *      named level; inputs must have zero boundary entries where stated. ---- */
+
+/* y = op x on level (helm_op; HELM_OP_Q only on level 0).  x, y must differ. */
+helm_status helm_apply(helm_hierarchy *H, int level, int op, const void *x, void *y);
+
+/* r = g - op x (op = HELM_OP_A or HELM_OP_B); boundary entries of r are zero. */
+helm_status helm_residual(helm_hierarchy *H, int level, int op, const void *g, const void *x, void *r);
+
+/* y = J_nJ(op, g; omega): nJ damped Jacobi sweeps from zero (eq. jacobi-map),
+ * diagonal of the same operator (PML and shift included). */
+helm_status helm_jacobi(helm_hierarchy *H, int level, int op, const void *g, int nJ, double omega, void *y);
+
+/* coarse = R fine (full weighting), fine on `level` (0 or 1), coarse on level+1. */
+helm_status helm_restrict(helm_hierarchy *H, int level, const void *fine, void *coarse);
+
+/* fine += P coarse (trilinear), coarse on `level` (1 or 2), fine on level-1. */
+helm_status helm_prolong_add(helm_hierarchy *H, int level, const void *coarse, void *fine);
+
+/* e = C_4h(q): m_4h CA-GMRES steps on B_4h from zero, right preconditioned by
+ * J_nJ4h(B_4h; omega_4h) (Sec. 3.2).  q, e on level 2, zero boundary. */
+helm_status helm_bottom(helm_hierarchy *H, const void *q, void *e);
+
+/* y = V^sigma_2h(q), one shifted 2h-4h cycle (eq. shifted-auxiliary-cycle). */
+helm_status helm_vcycle(helm_hierarchy *H, const void *q, void *y);
+
+/* e = K_2h(r): c_2h FGMRES(m_2h) cycles on A_2h from zero, right
+ * preconditioned by V^sigma_2h (eq. unshifted-middle-solve). */
+helm_status helm_coarse_solve(helm_hierarchy *H, const void *r, void *e);
+
+/* x = S_h(g; x0): one GMRES(m_h) cycle on A_h from x0 (NULL = zero), right
+ * preconditioned by J_nJh(A_h; omega_h) (Sec. 3.3).  x may equal x0. */
+helm_status helm_smooth(helm_hierarchy *H, const void *g, const void *x0, void *x);
+
+/* z = M_h^{-1} r, Algorithm 1.  r with zero boundary; z must not alias r. */
+helm_status helm_precond(helm_hierarchy *H, const void *r, void *z);
+
+/* Krylov vector kernel: out[j] = sum_i conj(V_j[i]) w[i] for j < k, and
+ * out[k] = ||w||^2 (imaginary part 0), accumulated in FP64.
+ *   V   HOST array of k DEVICE pointers (level vectors), 0 <= k <= 16
+ *   out HOST double[2*(k+1)] (complex pairs) */
+helm_status helm_vec_dots(helm_hierarchy *H, int level, int k, const void *const *V, const void *w, double *out);
+
+/* One Arnoldi orthogonalisation step (classical Gram-Schmidt, two passes):
+ * w <- (w - V h) / ||w - V h||, with h = V^* w accumulated over both passes.
+ *   V   HOST array of k DEVICE pointers (orthonormal level vectors), 1 <= k <= 16
+ *   out HOST double[2*(k+1)]: h_0..h_{k-1} then ||w - V h|| */
+helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const void *const *V, void *w,
+                                    double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

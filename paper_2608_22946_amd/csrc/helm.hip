@@ -1,0 +1,792 @@
+// Operator hierarchy, nested Krylov drivers and the C ABI (include/helm.h).
+//
+// Everything a solve does is enqueued on the caller's stream: the level
+// operators, transfers and vector kernels run on the GPU and the small dense
+// work (Givens rotations, back substitution, the s-step Gram solve) runs in
+// the last block of the reduction kernels, so a preconditioner application
+// (Algorithm 1) needs no host synchronisation.  The host reads one Krylov
+// state per outer Arnoldi step for the convergence test.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "helm_internal.h"
+
+using namespace helm;
+
+namespace {
+thread_local std::string g_thread_error;
+}
+
+struct helm_hierarchy {
+    helm_options opt;
+    helm_precision prec;
+    int nphys[3];
+    int n_pml;
+    double h, omega;
+    hipStream_t s;
+    Geom geom[3];
+    LevelArgs<float> Lf[3];
+    LevelArgs<double> Ld[3];
+    // device buffers carved from the caller's workspace
+    float *vel[3];
+    float *wf[3][3];
+    double *wd[3][3];
+    float *atab_f, *btab_f;
+    double *atab_d, *btab_d;
+    void *Vout[kMMax + 1], *Zout[kMMax];
+    void *Vs[kMMax + 1], *Zs[kMMax];
+    c64 *x64, *b64;
+    void *V2[kMMax + 1], *Z2[kMMax];
+    void *e2, *r2, *vy, *vr;
+    void *P4[kM4Max + 1], *Z4[kM4Max];
+    void *e4;
+    void *tmp[3];
+    KState *st_outer, *st_smooth, *st_k2h, *st_bottom, *st_hook;
+    RedBuf rb;
+    double *dscratch;     // small device result buffer (dots, velocity check)
+    KState *host_state;   // pinned host copy of a Krylov state
+    double *host_scratch; // pinned host doubles
+    std::string err;
+};
+
+namespace {
+
+helm_status fail(helm_hierarchy *H, helm_status st, const std::string &msg) {
+    if (H)
+        H->err = msg;
+    else
+        g_thread_error = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(H, HELM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define HIP_CHK(expr)                         \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) return e_;      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename X>
+    X *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        X *p = base ? reinterpret_cast<X *>(base + off) : nullptr;
+        off += count * sizeof(X);
+        return p;
+    }
+};
+
+void level_geom(const int N[3], int l, double h, Geom &g) {
+    const int s = 1 << l;
+    for (int a = 0; a < 3; ++a) g.n[a] = N[a] / s;
+    g.sx = g.n[0] + 1;
+    g.sy = (long long)(g.n[0] + 1) * (g.n[1] + 1);
+    g.nn = g.sy * (g.n[2] + 1);
+    g.ell = s * h;
+}
+
+// Lay out (or size, when base == nullptr) every device buffer.
+size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &o, int K) {
+    Carver c{base};
+    Geom g[3];
+    for (int l = 0; l < 3; ++l) level_geom(N, l, 1.0, g[l]);
+    const size_t es = (o.precision == HELM_FP64) ? sizeof(c64) : sizeof(c32);
+    auto vec = [&](int l) { return c.take<char>(es * (size_t)g[l].nn); };
+    helm_hierarchy dummy;
+    helm_hierarchy *Hp = H ? H : &dummy;
+    for (int l = 0; l < 3; ++l) {
+        Hp->vel[l] = c.take<float>(g[l].nn);
+        for (int a = 0; a < 3; ++a) {
+            Hp->wf[l][a] = c.take<float>(6 * (size_t)(g[l].n[a] + 1));
+            Hp->wd[l][a] = c.take<double>(6 * (size_t)(g[l].n[a] + 1));
+        }
+    }
+    Hp->atab_f = c.take<float>(20 * (size_t)K);
+    Hp->btab_f = c.take<float>(12 * (size_t)K);
+    Hp->atab_d = c.take<double>(20 * (size_t)K);
+    Hp->btab_d = c.take<double>(12 * (size_t)K);
+    for (int j = 0; j <= o.m_out; ++j) Hp->Vout[j] = vec(0);
+    for (int j = 0; j < o.m_out; ++j) Hp->Zout[j] = vec(0);
+    for (int j = 0; j <= o.m_h; ++j) Hp->Vs[j] = vec(0);
+    for (int j = 0; j < o.m_h; ++j) Hp->Zs[j] = vec(0);
+    Hp->x64 = c.take<c64>(g[0].nn);
+    Hp->b64 = c.take<c64>(g[0].nn);
+    for (int j = 0; j <= o.m_2h; ++j) Hp->V2[j] = vec(1);
+    for (int j = 0; j < o.m_2h; ++j) Hp->Z2[j] = vec(1);
+    Hp->e2 = vec(1);
+    Hp->r2 = vec(1);
+    Hp->vy = vec(1);
+    Hp->vr = vec(1);
+    for (int j = 0; j <= o.m_4h; ++j) Hp->P4[j] = vec(2);
+    for (int j = 0; j < o.m_4h; ++j) Hp->Z4[j] = vec(2);
+    Hp->e4 = vec(2);
+    for (int l = 0; l < 3; ++l) Hp->tmp[l] = vec(l);
+    Hp->st_outer = c.take<KState>(1);
+    Hp->st_smooth = c.take<KState>(1);
+    Hp->st_k2h = c.take<KState>(1);
+    Hp->st_bottom = c.take<KState>(1);
+    Hp->st_hook = c.take<KState>(1);
+    size_t np = (size_t)kRedBlocks * 2 * 48;
+    for (int l = 0; l < 3; ++l) np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2]));
+    Hp->rb.partials = c.take<double>(np);
+    Hp->rb.counter = c.take<unsigned>(64);
+    Hp->dscratch = c.take<double>(256);
+    return c.off + 256;
+}
+
+// Per-axis stretching of one level (eq. pml-profile): gamma at the nodes,
+// averaged to the half nodes before inversion; second-difference weights
+// wm = -xi_a^-1 xi_{a-1/2}^-1, wc = xi_a^-1 (xi_{a+1/2}^-1 + xi_{a-1/2}^-1),
+// wp = -xi_a^-1 xi_{a+1/2}^-1 (eq. pml-second-difference).
+void axis_weights(int n, double ell, double L, double Lpml, double gmax, std::vector<double> &w, int &lo, int &hi) {
+    std::vector<double> gam(n + 1);
+    for (int j = 0; j <= n; ++j) {
+        const double x = j * ell;
+        double d = 0.0;
+        if (Lpml > 0) {
+            d = std::max(0.0, std::max(Lpml - x, x - (L - Lpml)));
+            d = std::min(d, Lpml);
+            gam[j] = gmax * (1.0 - std::cos(M_PI * d / (2.0 * Lpml)));
+        } else {
+            gam[j] = 0.0;
+        }
+    }
+    auto inv = [](double g, double &re, double &im) {   // 1 / (1 + i g)
+        const double den = 1.0 + g * g;
+        re = 1.0 / den;
+        im = -g / den;
+    };
+    w.assign(6 * (size_t)(n + 1), 0.0);
+    for (int j = 1; j <= n - 1; ++j) {
+        double nr, ni, pr, pi, mr, mi;
+        inv(gam[j], nr, ni);
+        inv(0.5 * (gam[j] + gam[j + 1]), pr, pi);
+        inv(0.5 * (gam[j - 1] + gam[j]), mr, mi);
+        double *o = &w[6 * j];
+        o[0] = -(nr * mr - ni * mi);
+        o[1] = -(nr * mi + ni * mr);
+        o[2] = nr * (pr + mr) - ni * (pi + mi);
+        o[3] = nr * (pi + mi) + ni * (pr + mr);
+        o[4] = -(nr * pr - ni * pi);
+        o[5] = -(nr * pi + ni * pr);
+    }
+    lo = n;
+    hi = 0;
+    for (int j = 1; j <= n - 1; ++j)
+        if (gam[j - 1] == 0.0 && gam[j] == 0.0 && gam[j + 1] == 0.0) {
+            lo = std::min(lo, j);
+            hi = std::max(hi, j);
+        }
+}
+
+// Hermite nodes (value, slope) -> monomial coefficients in t on each interval
+void hermite_monomials(const double *tab, int K, int f0, int nf, std::vector<double> &out) {
+    const double de = 0.4 / K;
+    out.assign((size_t)K * nf * 4, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int f = 0; f < nf; ++f) {
+            const double p0 = tab[(k * 8 + f0 + f) * 2], m0 = de * tab[(k * 8 + f0 + f) * 2 + 1];
+            const double p1 = tab[((k + 1) * 8 + f0 + f) * 2], m1 = de * tab[((k + 1) * 8 + f0 + f) * 2 + 1];
+            double *c = &out[((size_t)k * nf + f) * 4];
+            c[0] = p0;
+            c[1] = m0;
+            c[2] = -3 * p0 - 2 * m0 + 3 * p1 - m1;
+            c[3] = 2 * p0 + m0 - 2 * p1 + m1;
+        }
+}
+
+template <typename R>
+void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, const R *wy, const R *wz, const R *at,
+                     const R *bt) {
+    const Geom &g = H->geom[l];
+    L.nx = g.n[0];
+    L.ny = g.n[1];
+    L.nz = g.n[2];
+    L.sx = g.sx;
+    L.sy = g.sy;
+    L.lox = g.lo[0]; L.hix = g.hi[0];
+    L.loy = g.lo[1]; L.hiy = g.hi[1];
+    L.loz = g.lo[2]; L.hiz = g.hi[2];
+    L.c = H->vel[l];
+    L.wx = wx;
+    L.wy = wy;
+    L.wz = wz;
+    L.atab = at;
+    L.btab = bt;
+    L.K = H->opt.iofd_K;
+    L.inv_deta = (R)(H->opt.iofd_K / 0.4);
+    L.omega_ell = (R)(H->omega * g.ell);
+    L.inv_ell2 = (R)(1.0 / (g.ell * g.ell));
+    L.sigma = (R)H->opt.sigma;
+}
+
+// ---------------------------------------------------------------------------
+// Precision-specific drivers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Eng {
+    using R = decltype(T{}.re);
+    helm_hierarchy *H;
+    hipStream_t s;
+
+    explicit Eng(helm_hierarchy *h) : H(h), s(h->s) {}
+
+    const LevelArgs<R> &L(int l) const;
+    long long nn(int l) const { return H->geom[l].nn; }
+    T *v(void *p) const { return static_cast<T *>(p); }
+
+    hipError_t stencil(int l, int mode, bool shifted, double wJ, const void *x, const void *g, const void *base,
+                       void *y, bool norm = false, KState *st = nullptr) {
+        StencilCall c{mode, shifted ? 1 : 0, wJ, x, g, base, y, norm, EPI_NORM_INIT, st, 0};
+        return launch_stencil<R, T, T, T>(L(l), c, H->rb, s);
+    }
+
+    // y = J_nJ(op, g; w) from zero; tmp is a scratch vector of the level
+    hipError_t jacobi(int l, bool shifted, int nJ, double w, const T *g, T *y) {
+        if (nJ == 1) return launch_jac1<R, T>(L(l), shifted, w, g, y, s);
+        HIP_CHK(stencil(l, M_JAC2, shifted, w, nullptr, g, nullptr, y));
+        T *a = y, *b = v(H->tmp[l]);
+        for (int it = 2; it < nJ; ++it) {
+            HIP_CHK(stencil(l, M_JSWEEP, shifted, w, a, g, nullptr, b));
+            std::swap(a, b);
+        }
+        if (a != y) HIP_CHK((launch_convert<T, T>(a, y, nn(l), s)));
+        return hipSuccess;
+    }
+
+    // Arnoldi step: V[k+1] <- A Z[k] orthonormalised against V[0..k] (CGS2), Givens update of column k
+    hipError_t arnoldi(int l, T **V, int k, KState *st) {
+        HIP_CHK(launch_dots<T>((const T *const *)V, k + 1, V[k + 1], false, nn(l), EPI_ARNOLDI1, st, k, nullptr, H->rb,
+                               s));
+        HIP_CHK(launch_axpy_dots<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, H->rb, s));
+        HIP_CHK(launch_axpy_scale<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, s));
+        return hipSuccess;
+    }
+
+    // `cycles` restarted right-preconditioned (F)GMRES(m) cycles for op x = g on level l
+    template <typename Prec>
+    hipError_t gmres(int l, bool shifted, Prec prec, const T *g, T *x, bool x0_zero, int m, int cycles, KState *st,
+                     void **Vv, void **Zv) {
+        T *V[kMMax + 1], *Zp[kMMax];
+        for (int j = 0; j <= m; ++j) V[j] = v(Vv[j]);
+        for (int j = 0; j < m; ++j) Zp[j] = v(Zv[j]);
+        for (int cyc = 0; cyc < cycles; ++cyc) {
+            const bool from_zero = (cyc == 0 && x0_zero);
+            if (from_zero)
+                HIP_CHK(launch_dots<T>(nullptr, 0, g, true, nn(l), EPI_NORM_INIT, st, 0, nullptr, H->rb, s));
+            else
+                HIP_CHK(stencil(l, M_RESID, shifted, 0.0, x, g, nullptr, V[0], true, st));
+            HIP_CHK(launch_scale<T>(from_zero ? g : V[0], V[0], nn(l), st, s));
+            for (int k = 0; k < m; ++k) {
+                HIP_CHK(prec(V[k], Zp[k]));
+                HIP_CHK(stencil(l, M_APPLY, shifted, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
+                HIP_CHK(arnoldi(l, V, k, st));
+            }
+            HIP_CHK((launch_combine<T, T>(x, (const T *const *)Zp, m, nn(l), st, true, from_zero, s)));
+        }
+        return hipSuccess;
+    }
+
+    // C_4h: m_4h s-step (CA-GMRES) steps on B_4h from zero, right preconditioned by
+    // J_nJ4h(B_4h; omega_4h).  Basis P_0 = q, P_{j+1} = B_4h J(P_j); the iterate
+    // sum_j y_j J(P_j) minimises ||q - sum_j y_j P_{j+1}|| (normal equations of the
+    // FP64 Gram matrix, Cholesky).
+    hipError_t bottom(const T *q, T *e) {
+        const int m = H->opt.m_4h;
+        T *P[kM4Max + 1], *Zb[kM4Max];
+        P[0] = const_cast<T *>(q);
+        for (int j = 1; j <= m; ++j) P[j] = v(H->P4[j]);
+        for (int j = 0; j < m; ++j) Zb[j] = v(H->Z4[j]);
+        for (int j = 0; j < m; ++j) {
+            HIP_CHK(jacobi(2, true, H->opt.nJ_4h, H->opt.omega_4h, P[j], Zb[j]));
+            HIP_CHK(stencil(2, M_APPLY, true, 0.0, Zb[j], nullptr, nullptr, P[j + 1]));
+        }
+        HIP_CHK(launch_gram<T>((const T *const *)P, m + 1, nn(2), H->st_bottom, H->rb, s));
+        HIP_CHK((launch_combine<T, T>(e, (const T *const *)Zb, m, nn(2), H->st_bottom, false, true, s)));
+        return hipSuccess;
+    }
+
+    // V^sigma_2h(q), eq. shifted-auxiliary-cycle
+    hipError_t vcycle(const T *q, T *out) {
+        const helm_options &o = H->opt;
+        T *y = v(H->vy), *r = v(H->vr), *q4 = v(H->P4[0]), *e4 = v(H->e4);
+        HIP_CHK(jacobi(1, true, o.nJ_2h, o.omega_2h, q, y));                 // y = J(B_2h, q)
+        HIP_CHK(stencil(1, M_RESID, true, 0.0, y, q, nullptr, r));           // q - B y
+        HIP_CHK(launch_restrict<T>(H->geom[1], H->geom[2], r, q4, s));      // q_4h = R(q - B y)
+        HIP_CHK(bottom(q4, e4));                                             // e_4h = C_4h(q_4h)
+        HIP_CHK(launch_prolong_add<T>(H->geom[2], H->geom[1], e4, y, s));   // y~ = y + P e_4h
+        HIP_CHK(stencil(1, M_RESID, true, 0.0, y, q, nullptr, r));           // q - B y~
+        if (o.nJ_2h == 2) {
+            HIP_CHK(stencil(1, M_JAC2_ADD, true, o.omega_2h, nullptr, r, y, out));   // y~ + J(B, q - B y~)
+        } else {
+            HIP_CHK(jacobi(1, true, o.nJ_2h, o.omega_2h, r, out));
+            HIP_CHK(launch_add<T>(y, out, nn(1), s));
+        }
+        return hipSuccess;
+    }
+
+    // K_2h(r), eq. unshifted-middle-solve
+    hipError_t k2h(const T *r, T *e) {
+        auto prec = [this](const T *in, T *out) { return vcycle(in, out); };
+        return gmres(1, false, prec, r, e, true, H->opt.m_2h, H->opt.c_2h, H->st_k2h, H->V2, H->Z2);
+    }
+
+    // S_h(g; x0) -> x (in place when x0 == x)
+    hipError_t smooth(const T *g, T *x, bool x0_zero) {
+        auto prec = [this](const T *in, T *out) {
+            return jacobi(0, false, H->opt.nJ_h, H->opt.omega_h, in, out);
+        };
+        return gmres(0, false, prec, g, x, x0_zero, H->opt.m_h, 1, H->st_smooth, H->Vs, H->Zs);
+    }
+
+    // Algorithm 1: z = M_h^{-1} r
+    hipError_t precond(const T *r, T *z) {
+        T *t = v(H->Vs[0]), *r2 = v(H->r2), *e2 = v(H->e2);
+        HIP_CHK(smooth(r, z, true));                                          // 1: z_pre = S_h(r; 0)
+        HIP_CHK(stencil(0, M_RESID, false, 0.0, z, r, nullptr, t));          // 2: r_2h = R(r - A z_pre)
+        HIP_CHK(launch_restrict<T>(H->geom[0], H->geom[1], t, r2, s));
+        HIP_CHK(k2h(r2, e2));                                                 // 3: e_2h = K_2h(r_2h)
+        HIP_CHK(launch_prolong_add<T>(H->geom[1], H->geom[0], e2, z, s));    // 4: z~ = z_pre + P e_2h
+        HIP_CHK(smooth(r, z, false));                                         // 5: z = S_h(r; z~)
+        return hipSuccess;
+    }
+
+    hipError_t read_state(const KState *st) {
+        HIP_CHK(hipMemcpyAsync(H->host_state, st, sizeof(KState), hipMemcpyDeviceToHost, s));
+        return hipStreamSynchronize(s);
+    }
+
+    // Outer FGMRES(m_out) for one right-hand side (Sec. 3.3); x and b in FP64.
+    helm_status solve_one(const T *f, T *u, double tol, int *iters, double *relres) {
+        const helm_options &o = H->opt;
+        const long long n = nn(0);
+        T *V[kMMax + 1], *Zp[kMMax];
+        for (int j = 0; j <= o.m_out; ++j) V[j] = v(H->Vout[j]);
+        for (int j = 0; j < o.m_out; ++j) Zp[j] = v(H->Zout[j]);
+        KState *st = H->st_outer;
+        const int max_outer = o.max_outer > 0 ? o.max_outer : 1000;
+        HIP_TRY((launch_qapply<double, T, c64>(H->Ld[0], f, H->b64, s)));   // b = Q_h f
+        HIP_TRY(launch_dots<c64>(nullptr, 0, H->b64, true, n, EPI_STORE, nullptr, 0, H->dscratch, H->rb, s));
+        HIP_TRY(hipMemcpyAsync(H->host_scratch, H->dscratch, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const double bn = std::sqrt(H->host_scratch[0]);
+        HIP_TRY(launch_fill_zero<c64>(H->x64, n, s));
+        int its = 0;
+        double rel = 0.0;
+        helm_status status = HELM_OK;
+        if (!(bn == bn) || bn > 1e300) return fail(H, HELM_BREAKDOWN, "non-finite right-hand side");
+        if (bn == 0.0) {
+            HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], H->x64, u, s)));
+            *iters = 0;
+            *relres = 0.0;
+            return HELM_OK;
+        }
+        for (;;) {
+            // true residual in FP64 arithmetic: r = b - A_h x
+            StencilCall c{M_RESID, 0, 0.0, H->x64, H->b64, nullptr, V[0], true, EPI_NORM_INIT, st, 0};
+            HIP_TRY((launch_stencil<double, c64, c64, T>(H->Ld[0], c, H->rb, s)));
+            HIP_TRY(read_state(st));
+            if (H->host_state->nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite residual");
+            rel = H->host_state->beta / bn;
+            if (rel <= tol) break;
+            if (its >= max_outer) {
+                status = HELM_NOT_CONVERGED;
+                break;
+            }
+            HIP_TRY(launch_scale<T>(V[0], V[0], n, st, s));
+            int kk = 0;
+            for (int k = 0; k < o.m_out; ++k) {
+                HIP_TRY(precond(V[k], Zp[k]));
+                ++its;
+                HIP_TRY(stencil(0, M_APPLY, false, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
+                HIP_TRY(arnoldi(0, V, k, st));
+                HIP_TRY(read_state(st));
+                kk = k + 1;
+                const KState &hs = *H->host_state;
+                if (hs.nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite Krylov quantity");
+                const double est = std::hypot(hs.g[k + 1][0], hs.g[k + 1][1]) / bn;
+                if (est <= tol || hs.breakdown || its >= max_outer) break;
+            }
+            HIP_TRY((launch_combine<c64, T>(H->x64, (const T *const *)Zp, kk, n, st, true, false, s)));
+        }
+        HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], H->x64, u, s)));   // u = Q_h v
+        HIP_TRY(hipStreamSynchronize(s));
+        *iters = its;
+        *relres = rel;
+        return status;
+    }
+};
+
+template <>
+const LevelArgs<float> &Eng<c32>::L(int l) const { return H->Lf[l]; }
+template <>
+const LevelArgs<double> &Eng<c64>::L(int l) const { return H->Ld[l]; }
+
+helm_status check_options(const helm_options *o, std::string &msg) {
+    if (!o) { msg = "options pointer is NULL"; return HELM_EINVAL; }
+    if (o->struct_size != (int)sizeof(helm_options)) { msg = "options.struct_size mismatch"; return HELM_EINVAL; }
+    if (o->precision != HELM_FP64 && o->precision != HELM_FP32) { msg = "unknown precision"; return HELM_EINVAL; }
+    if (!(o->sigma >= 0) || !(o->omega_h > 0) || !(o->omega_2h > 0) || !(o->omega_4h > 0) || !(o->gamma_max >= 0) ||
+        !std::isfinite(o->sigma) || !std::isfinite(o->gamma_max)) {
+        msg = "sigma, Jacobi weights and gamma_max must be finite (weights > 0)";
+        return HELM_EINVAL;
+    }
+    auto in = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
+    if (!in(o->nJ_h, 1, 8) || !in(o->nJ_2h, 1, 8) || !in(o->nJ_4h, 1, 8)) { msg = "nJ must be in 1..8"; return HELM_EINVAL; }
+    if (!in(o->m_h, 1, kMMax) || !in(o->m_2h, 1, kMMax) || !in(o->m_out, 1, kMMax)) {
+        msg = "m_h, m_2h and m_out must be in 1..12";
+        return HELM_EINVAL;
+    }
+    if (!in(o->m_4h, 1, kM4Max) || !in(o->c_2h, 1, 8)) { msg = "m_4h must be in 1..8 and c_2h in 1..8"; return HELM_EINVAL; }
+    if (!in(o->iofd_K, 1, kKMax)) { msg = "iofd_K must be in 1..128"; return HELM_EINVAL; }
+    return HELM_OK;
+}
+
+helm_status check_dims(int nx, int ny, int nz, int n_pml, int N[3], std::string &msg) {
+    if (nx < 1 || ny < 1 || nz < 1 || n_pml < 0) { msg = "grid sizes must be positive and n_pml >= 0"; return HELM_EINVAL; }
+    const int n[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        const long long t = (long long)n[a] + 2LL * n_pml;
+        if (t % 4 != 0 || t < 8 || t > 4096) {
+            msg = "total intervals per axis (n + 2 n_pml) must be a multiple of 4 in [8, 4096]";
+            return HELM_EINVAL;
+        }
+        N[a] = (int)t;
+    }
+    return HELM_OK;
+}
+
+template <typename F>
+helm_status dispatch(helm_hierarchy *H, F &&f) {
+    hipError_t e = (H->prec == HELM_FP64) ? f(Eng<c64>(H)) : f(Eng<c32>(H));
+    if (e != hipSuccess) return fail(H, HELM_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return HELM_OK;
+}
+
+bool level_ok(int l) { return l >= 0 && l <= 2; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+helm_status helm_default_options(helm_options *o) {
+    if (!o) return fail(nullptr, HELM_EINVAL, "options pointer is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(helm_options);
+    o->precision = HELM_FP32;
+    o->sigma = 0.9;
+    o->omega_h = 0.8;
+    o->omega_2h = 0.8;
+    o->omega_4h = 0.2;
+    o->gamma_max = 1.119058;
+    o->nJ_h = o->nJ_2h = o->nJ_4h = 2;
+    o->m_h = 2;
+    o->c_2h = 2;
+    o->m_2h = 10;
+    o->m_4h = 4;
+    o->m_out = 5;
+    o->max_outer = 1000;
+    o->iofd_table = nullptr;
+    o->iofd_K = 0;
+    o->stream = nullptr;
+    return HELM_OK;
+}
+
+helm_status helm_workspace_size(int nx, int ny, int nz, int n_pml, const helm_options *opt, size_t *bytes) {
+    std::string msg;
+    int N[3];
+    helm_status st = check_options(opt, msg);
+    if (st == HELM_OK) st = check_dims(nx, ny, nz, n_pml, N, msg);
+    if (st == HELM_OK && !bytes) { msg = "bytes pointer is NULL"; st = HELM_EINVAL; }
+    if (st != HELM_OK) return fail(nullptr, st, msg);
+    *bytes = carve(nullptr, nullptr, N, *opt, opt->iofd_K);
+    return HELM_OK;
+}
+
+helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, double omega, int n_pml,
+                       const helm_options *opt, void *workspace, size_t ws_bytes, helm_hierarchy **out) {
+    std::string msg;
+    int N[3];
+    helm_status st = check_options(opt, msg);
+    if (st == HELM_OK) st = check_dims(nx, ny, nz, n_pml, N, msg);
+    if (st == HELM_OK && (!velocity || !out)) { msg = "velocity and out must not be NULL"; st = HELM_EINVAL; }
+    if (st == HELM_OK && (!(h > 0) || !(omega > 0) || !std::isfinite(h) || !std::isfinite(omega))) {
+        msg = "h and omega must be finite and positive";
+        st = HELM_EINVAL;
+    }
+    if (st == HELM_OK && !opt->iofd_table) { msg = "options.iofd_table is required"; st = HELM_EINVAL; }
+    if (st == HELM_OK) {
+        for (int i = 0; i < (opt->iofd_K + 1) * 16; ++i)
+            if (!std::isfinite(opt->iofd_table[i])) { msg = "iofd_table holds a non-finite value"; st = HELM_EINVAL; break; }
+    }
+    if (st != HELM_OK) return fail(nullptr, st, msg);
+    const size_t need = carve(nullptr, nullptr, N, *opt, opt->iofd_K);
+    if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return fail(nullptr, HELM_EWORKSPACE, "workspace missing, smaller than helm_workspace_size() or not 256-byte aligned");
+
+    helm_hierarchy *H = new helm_hierarchy();
+    H->opt = *opt;
+    H->prec = opt->precision;
+    H->nphys[0] = nx; H->nphys[1] = ny; H->nphys[2] = nz;
+    H->n_pml = n_pml;
+    H->h = h;
+    H->omega = omega;
+    H->s = static_cast<hipStream_t>(opt->stream);
+    carve(H, static_cast<char *>(workspace), N, *opt, opt->iofd_K);
+    H->opt.iofd_table = nullptr;   // copied below, not retained
+
+    auto bail = [&](helm_status code, const std::string &m) {
+        g_thread_error = m;
+        if (H->host_state) (void)hipHostFree(H->host_state);
+        if (H->host_scratch) (void)hipHostFree(H->host_scratch);
+        delete H;
+        return code;
+    };
+    hipError_t e;
+    if ((e = hipHostMalloc((void **)&H->host_state, sizeof(KState))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&H->host_scratch, 64 * sizeof(double))) != hipSuccess)
+        return bail(HELM_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    hipStream_t s = H->s;
+    // counters start at zero
+    if ((e = hipMemsetAsync(H->rb.counter, 0, 64 * sizeof(unsigned), s)) != hipSuccess)
+        return bail(HELM_EHIP, hipGetErrorString(e));
+    // velocity must be finite and positive
+    const long long nphys = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+    if ((e = launch_velocity_check(velocity, nphys, H->rb, H->dscratch, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(H->host_scratch, H->dscratch, 3 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(HELM_EHIP, std::string("velocity check: ") + hipGetErrorString(e));
+    if (H->host_scratch[2] != 0.0 || !(H->host_scratch[0] > 0.0))
+        return bail(HELM_EINVAL, "velocity must be finite and positive everywhere");
+
+    const double Lpml = n_pml * h;
+    std::vector<double> w;
+    std::vector<float> wfv;
+    for (int l = 0; l < 3; ++l) {
+        Geom &g = H->geom[l];
+        level_geom(N, l, h, g);
+        for (int a = 0; a < 3; ++a) {
+            axis_weights(g.n[a], g.ell, N[a] * h, Lpml, opt->gamma_max, w, g.lo[a], g.hi[a]);
+            wfv.assign(w.begin(), w.end());
+            if ((e = hipMemcpyAsync(H->wd[l][a], w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(H->wf[l][a], wfv.data(), wfv.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return bail(HELM_EHIP, std::string("upload: ") + hipGetErrorString(e));
+        }
+        if ((e = launch_extend_velocity(velocity, H->nphys, n_pml, 1 << l, g, H->vel[l], s)) != hipSuccess)
+            return bail(HELM_EHIP, hipGetErrorString(e));
+    }
+    std::vector<double> at, bt;
+    hermite_monomials(opt->iofd_table, opt->iofd_K, 0, 5, at);
+    hermite_monomials(opt->iofd_table, opt->iofd_K, 5, 3, bt);
+    std::vector<float> atf(at.begin(), at.end()), btf(bt.begin(), bt.end());
+    if ((e = hipMemcpyAsync(H->atab_d, at.data(), at.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(H->btab_d, bt.data(), bt.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(H->atab_f, atf.data(), atf.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(H->btab_f, btf.data(), btf.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(HELM_EHIP, std::string("table upload: ") + hipGetErrorString(e));
+    for (int l = 0; l < 3; ++l) {
+        fill_level_args<float>(H, l, H->Lf[l], H->wf[l][0], H->wf[l][1], H->wf[l][2], H->atab_f, H->btab_f);
+        fill_level_args<double>(H, l, H->Ld[l], H->wd[l][0], H->wd[l][1], H->wd[l][2], H->atab_d, H->btab_d);
+    }
+    *out = H;
+    return HELM_OK;
+}
+
+helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, int *iters, double *relres) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!f || !u || !iters || !relres || nrhs < 0 || !(tol > 0) || !std::isfinite(tol))
+        return fail(H, HELM_EINVAL, "invalid solve arguments");
+    if (f == u) return fail(H, HELM_EINVAL, "f and u must not alias");
+    const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
+    const long long n = H->geom[0].nn;
+    helm_status worst = HELM_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const char *fr = static_cast<const char *>(f) + (size_t)r * n * es;
+        char *ur = static_cast<char *>(u) + (size_t)r * n * es;
+        helm_status st = (H->prec == HELM_FP64)
+                             ? Eng<c64>(H).solve_one((const c64 *)fr, (c64 *)ur, tol, iters + r, relres + r)
+                             : Eng<c32>(H).solve_one((const c32 *)fr, (c32 *)ur, tol, iters + r, relres + r);
+        if (st < 0) return st;
+        if (st == HELM_NOT_CONVERGED) worst = st;
+    }
+    return worst;
+}
+
+helm_status helm_grad(helm_hierarchy *H, const void *, int, double, float *) {
+    return fail(H, HELM_ENOTIMPL, "helm_grad is not available in this version");
+}
+
+void helm_destroy(helm_hierarchy *H) {
+    if (!H) return;
+    if (H->host_state) (void)hipHostFree(H->host_state);
+    if (H->host_scratch) (void)hipHostFree(H->host_scratch);
+    delete H;
+}
+
+const char *helm_last_error(const helm_hierarchy *H) { return H ? H->err.c_str() : g_thread_error.c_str(); }
+
+helm_status helm_dims(const helm_hierarchy *H, int level, int dims[3]) {
+    if (!H || !dims || !level_ok(level)) return fail(const_cast<helm_hierarchy *>(H), HELM_EINVAL, "invalid arguments");
+    for (int a = 0; a < 3; ++a) dims[a] = H->geom[level].n[a];
+    return HELM_OK;
+}
+
+helm_status helm_apply(helm_hierarchy *H, int level, int op, const void *x, void *y) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!level_ok(level) || op < 0 || op > 4 || (op == HELM_OP_Q && level != 0) || !x || !y || x == y)
+        return fail(H, HELM_EINVAL, "invalid apply arguments");
+    return dispatch(H, [&](auto E) -> hipError_t {
+        using T = typename std::remove_reference<decltype(E)>::type;
+        using V = decltype(*E.v(nullptr));
+        using TT = typename std::remove_reference<V>::type;
+        if (op == HELM_OP_A || op == HELM_OP_B)
+            return E.stencil(level, M_APPLY, op == HELM_OP_B, 0.0, x, nullptr, nullptr, y);
+        if (op == HELM_OP_Q)
+            return launch_qapply<typename T::R, TT, TT>(E.L(0), (const TT *)x, (TT *)y, E.s);
+        return launch_diag<typename T::R, TT>(E.L(level), op == HELM_OP_DIAG_B, (const TT *)x, (TT *)y, E.s);
+    });
+}
+
+helm_status helm_residual(helm_hierarchy *H, int level, int op, const void *g, const void *x, void *r) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!level_ok(level) || (op != HELM_OP_A && op != HELM_OP_B) || !g || !x || !r || r == x || r == g)
+        return fail(H, HELM_EINVAL, "invalid residual arguments");
+    return dispatch(H, [&](auto E) { return E.stencil(level, M_RESID, op == HELM_OP_B, 0.0, x, g, nullptr, r); });
+}
+
+helm_status helm_jacobi(helm_hierarchy *H, int level, int op, const void *g, int nJ, double omega, void *y) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!level_ok(level) || (op != HELM_OP_A && op != HELM_OP_B) || !g || !y || g == y || nJ < 1 || nJ > 64 ||
+        !std::isfinite(omega))
+        return fail(H, HELM_EINVAL, "invalid jacobi arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return E.jacobi(level, op == HELM_OP_B, nJ, omega, (const TT *)g, (TT *)y);
+    });
+}
+
+helm_status helm_restrict(helm_hierarchy *H, int level, const void *fine, void *coarse) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (level < 0 || level > 1 || !fine || !coarse) return fail(H, HELM_EINVAL, "invalid restrict arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return launch_restrict<TT>(H->geom[level], H->geom[level + 1], (const TT *)fine, (TT *)coarse, E.s);
+    });
+}
+
+helm_status helm_prolong_add(helm_hierarchy *H, int level, const void *coarse, void *fine) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (level < 1 || level > 2 || !fine || !coarse) return fail(H, HELM_EINVAL, "invalid prolong arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return launch_prolong_add<TT>(H->geom[level], H->geom[level - 1], (const TT *)coarse, (TT *)fine, E.s);
+    });
+}
+
+helm_status helm_bottom(helm_hierarchy *H, const void *q, void *e) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!q || !e || q == e) return fail(H, HELM_EINVAL, "invalid bottom arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return E.bottom((const TT *)q, (TT *)e);
+    });
+}
+
+helm_status helm_vcycle(helm_hierarchy *H, const void *q, void *y) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!q || !y || q == y) return fail(H, HELM_EINVAL, "invalid vcycle arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return E.vcycle((const TT *)q, (TT *)y);
+    });
+}
+
+helm_status helm_coarse_solve(helm_hierarchy *H, const void *r, void *e) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!r || !e || r == e) return fail(H, HELM_EINVAL, "invalid coarse-solve arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return E.k2h((const TT *)r, (TT *)e);
+    });
+}
+
+helm_status helm_smooth(helm_hierarchy *H, const void *g, const void *x0, void *x) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!g || !x || g == x) return fail(H, HELM_EINVAL, "invalid smooth arguments");
+    return dispatch(H, [&](auto E) -> hipError_t {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        if (x0 && x0 != x) HIP_CHK((launch_convert<TT, TT>((const TT *)x0, (TT *)x, E.nn(0), E.s)));
+        return E.smooth((const TT *)g, (TT *)x, x0 == nullptr);
+    });
+}
+
+helm_status helm_precond(helm_hierarchy *H, const void *r, void *z) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!r || !z || r == z) return fail(H, HELM_EINVAL, "invalid precond arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return E.precond((const TT *)r, (TT *)z);
+    });
+}
+
+helm_status helm_vec_dots(helm_hierarchy *H, int level, int k, const void *const *V, const void *w, double *out) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!level_ok(level) || k < 0 || k > kMMax || (k > 0 && !V) || !w || !out)
+        return fail(H, HELM_EINVAL, "invalid dots arguments");
+    helm_status st = dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return launch_dots<TT>((const TT *const *)V, k, (const TT *)w, true, E.nn(level), EPI_STORE, nullptr, 0,
+                               H->dscratch, H->rb, E.s);
+    });
+    if (st != HELM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(H->host_scratch, H->dscratch, 2 * (k + 1) * sizeof(double), hipMemcpyDeviceToHost, H->s));
+    HIP_TRY(hipStreamSynchronize(H->s));
+    std::memcpy(out, H->host_scratch, 2 * (k + 1) * sizeof(double));
+    return HELM_OK;
+}
+
+helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const void *const *V, void *w, double *out) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!level_ok(level) || k < 1 || k > kMMax || !V || !w || !out)
+        return fail(H, HELM_EINVAL, "invalid orthonormalize arguments");
+    HIP_TRY(hipMemsetAsync(H->st_hook, 0, sizeof(KState), H->s));
+    helm_status st = dispatch(H, [&](auto E) -> hipError_t {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        const TT *const *VV = (const TT *const *)V;
+        HIP_CHK(launch_dots<TT>(VV, k, (const TT *)w, false, E.nn(level), EPI_ARNOLDI1, H->st_hook, 0, nullptr, H->rb,
+                                E.s));
+        HIP_CHK(launch_axpy_dots<TT>(VV, k, (TT *)w, E.nn(level), H->st_hook, H->rb, E.s));
+        return launch_axpy_scale<TT>(VV, k, (TT *)w, E.nn(level), H->st_hook, E.s);
+    });
+    if (st != HELM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(H->host_state, H->st_hook, sizeof(KState), hipMemcpyDeviceToHost, H->s));
+    HIP_TRY(hipStreamSynchronize(H->s));
+    for (int j = 0; j < k; ++j) {
+        out[2 * j] = H->host_state->h1[j][0] + H->host_state->h2[j][0];
+        out[2 * j + 1] = H->host_state->h1[j][1] + H->host_state->h2[j][1];
+    }
+    out[2 * k] = H->host_state->hk1;
+    out[2 * k + 1] = 0.0;
+    return HELM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Internal declarations of the MI355X IOFD Helmholtz library (device types,
+// per-level kernel arguments, Krylov state and the kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "helm.h"
+
+namespace helm {
+
+constexpr int kMMax = 12;       // longest Krylov restart supported (m_h, m_2h, m_out)
+constexpr int kM4Max = 8;       // longest bottom (s-step) basis
+constexpr int kKMax = 128;      // most table intervals
+constexpr int kTileX = 62;      // output nodes per wavefront along x (64 lanes, 1-node halo each side)
+constexpr int kWavesY = 4;      // wavefronts (rows y) per workgroup
+constexpr int kRedBlocks = 1024;
+constexpr int kRedStride = kMMax + 2;   // partial-sum slots per block (dots + norm)
+constexpr double kBreakdown = 1e-14;    // happy-breakdown threshold h_{k+1,k} <= 1e-14 beta
+
+template <typename R>
+struct cplx {
+    R re, im;
+};
+using c32 = cplx<float>;
+using c64 = cplx<double>;
+
+// ---------------------------------------------------------------------------
+// Geometry and per-level kernel arguments
+// ---------------------------------------------------------------------------
+struct Geom {
+    int n[3];            // intervals per axis on this level
+    long long sx, sy;    // node strides of y and z
+    long long nn;        // nodes
+    int lo[3], hi[3];    // nodes a with unit stretching at a, a-1/2, a+1/2 (weights exactly -1, 2, -1)
+    double ell;
+};
+
+template <typename R>
+struct LevelArgs {
+    int nx, ny, nz;
+    long long sx, sy;
+    int lox, hix, loy, hiy, loz, hiz;
+    const float *c;      // velocity at the level nodes
+    const R *wx, *wy, *wz;  // per node: (wm.re, wm.im, wc.re, wc.im, wp.re, wp.im)
+    const R *atab;       // [K][5][4] monomial coefficients of alpha1..5 in t on each interval
+    const R *btab;       // [K][3][4] same for beta1..3
+    int K;
+    R inv_deta;          // K / 0.4
+    R omega_ell;         // omega * ell
+    R inv_ell2;
+    R sigma;
+};
+
+// ---------------------------------------------------------------------------
+// Krylov state kept in device memory (one per nested solver)
+// ---------------------------------------------------------------------------
+struct KState {
+    double H[kMMax + 1][kMMax][2];   // rotated Hessenberg (upper triangle = R factor)
+    double cs[kMMax];
+    double sn[kMMax][2];
+    double g[kMMax + 1][2];          // rotated beta e1
+    double h1[kMMax + 1][2];         // first Gram-Schmidt pass coefficients
+    double h2[kMMax + 1][2];         // second pass coefficients
+    double y[kMMax][2];              // combination coefficients (bottom solver)
+    double beta;                     // initial residual norm of the cycle
+    double scale;                    // multiplier that normalises the newest basis vector
+    double hk1;                      // last subdiagonal entry
+    int kk;                          // Arnoldi columns in the current cycle
+    int breakdown;
+    int nonfinite;
+    int pad;
+};
+
+struct RedBuf {
+    double *partials;    // [kRedBlocks][kRedStride][2]
+    unsigned *counter;   // zero between kernels
+};
+
+enum Mode { M_APPLY = 0, M_RESID = 1, M_JSWEEP = 2, M_JAC2 = 3, M_JAC2_ADD = 4 };
+
+enum Epi {
+    EPI_STORE = 0,       // write sums to out
+    EPI_NORM_INIT = 1,   // beta = sqrt(norm); reset the Krylov state; scale = 1/beta
+    EPI_ARNOLDI1 = 2,    // h1 = dots
+    EPI_ARNOLDI2 = 3,    // h = h1 + h2, subdiagonal, Givens update of column k
+    EPI_GRAM = 4         // s-step Gram matrix -> least-squares coefficients y
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (stencil.hip, transfer.hip, vector.hip)
+// ---------------------------------------------------------------------------
+struct StencilCall {
+    int mode;            // Mode
+    int shifted;         // 0: A (mu = 1), 1: B (mu = 1 + i sigma)
+    double omegaJ;       // Jacobi weight (JSWEEP, JAC2)
+    const void *x;       // operand (APPLY, RESID, JSWEEP)
+    const void *g;       // right-hand side (RESID, JSWEEP, JAC2)
+    const void *base;    // JAC2_ADD: y = base + J2(g)
+    void *y;
+    bool norm;           // accumulate ||y||^2 into the reduction epilogue
+    int epi;
+    KState *st;
+    int k;
+};
+
+// R = arithmetic type, TX/TG/TY = element types of x, g, y (c32 or c64)
+template <typename R, typename TX, typename TG, typename TY>
+hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, hipStream_t s);
+
+template <typename R, typename TI, typename TO>
+hipError_t launch_qapply(const LevelArgs<R> &L, const TI *x, TO *y, hipStream_t s);
+
+template <typename R, typename T>
+hipError_t launch_diag(const LevelArgs<R> &L, int shifted, const T *x, T *y, hipStream_t s);
+
+template <typename T>
+hipError_t launch_restrict(const Geom &fine, const Geom &coarse, const T *f, T *c, hipStream_t s);
+
+template <typename T>
+hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, T *f, hipStream_t s);
+
+template <typename T>
+hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long long n, int epi, KState *st, int k,
+                       double *out, const RedBuf &rb, hipStream_t s);
+
+template <typename T>
+hipError_t launch_axpy_dots(const T *const *V, int nv, T *w, long long n, KState *st, const RedBuf &rb,
+                            hipStream_t s);
+
+template <typename T>
+hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KState *st, hipStream_t s);
+
+template <typename T>
+hipError_t launch_scale(const T *x, T *y, long long n, const KState *st, hipStream_t s);
+
+// x (+)= sum_j y_j Z_j with y from the state: back substitution of the
+// rotated Hessenberg (from_backsolve) or the stored s-step coefficients.
+template <typename TX, typename TZ>
+hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, const KState *st, bool from_backsolve,
+                          bool overwrite, hipStream_t s);
+
+template <typename T>
+hipError_t launch_gram(const T *const *P, int np, long long n, KState *st, const RedBuf &rb, hipStream_t s);
+
+template <typename T>
+hipError_t launch_fill_zero(T *x, long long n, hipStream_t s);
+
+template <typename T>
+hipError_t launch_add(const T *x, T *y, long long n, hipStream_t s);   // y += x
+
+template <typename R, typename T>
+hipError_t launch_jac1(const LevelArgs<R> &L, int shifted, double omegaJ, const T *g, T *y, hipStream_t s);
+
+int stencil_blocks(int nx, int ny, int nz);   // grid size of launch_stencil on a level
+
+template <typename TI, typename TO>
+hipError_t launch_convert(const TI *x, TO *y, long long n, hipStream_t s);
+
+hipError_t launch_extend_velocity(const float *phys, const int nphys[3], int n_pml, int stride_fine,
+                                  const Geom &g, float *out, hipStream_t s);
+
+hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, double *out, hipStream_t s);
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace helm

@@ -1,0 +1,722 @@
+// Krylov vector kernels of the nested (F)GMRES iterations (Sec. 3.2, 3.3):
+// multi-dot products, the two classical Gram-Schmidt passes of one Arnoldi
+// step, normalisation, the final combination x += Z y, and the Gram matrix of
+// the s-step basis of the bottom solver.  All sums are accumulated in FP64 and
+// reduced deterministically: every block writes its partial sums, the last
+// block to finish (atomic ticket) adds them in a fixed order and runs the
+// small dense epilogue (Givens rotation, back substitution, Cholesky) in FP64,
+// so that no host synchronisation is needed inside a preconditioner call.
+#include <algorithm>
+
+#include "helm_internal.h"
+
+namespace helm {
+
+constexpr int kGramMax = (kM4Max + 1) * (kM4Max + 2) / 2;   // 45
+constexpr int kSlots = kGramMax > kRedStride ? kGramMax : kRedStride;
+
+namespace {
+
+template <typename T>
+using real_of = decltype(T{}.re);
+
+struct D2 {
+    double r, i;
+};
+
+__device__ __forceinline__ D2 operator+(D2 a, D2 b) { return {a.r + b.r, a.i + b.i}; }
+
+template <typename T>
+__device__ __forceinline__ D2 cdot(T a, T b) {   // conj(a) * b
+    const double ar = a.re, ai = a.im, br = b.re, bi = b.im;
+    return {ar * br + ai * bi, ar * bi - ai * br};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-reduce NS complex sums, store them as this block's partials, then
+// return true in the last block (whose threads see every block's partials).
+template <int NS>
+__device__ bool reduce_partials(D2 (&acc)[NS], const RedBuf &rb) {
+    __shared__ double red[4][2 * kSlots];
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        double r = wave_sum(acc[s].r), i = wave_sum(acc[s].i);
+        if (lane == 0) {
+            red[w][2 * s] = r;
+            red[w][2 * s + 1] = i;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NS) {
+        double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        rb.partials[(size_t)blockIdx.x * 2 * kSlots + threadIdx.x] = v;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(rb.counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// In the last block: total of slot s over all blocks (fixed order), into out[s].
+template <int NS>
+__device__ void sum_partials(const RedBuf &rb, D2 *out) {
+    __shared__ double tree[256];
+    const int nb = gridDim.x;
+    for (int q = 0; q < 2 * NS; ++q) {
+        double v = 0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            v += __hip_atomic_load(rb.partials + (size_t)b * 2 * kSlots + q, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        tree[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off) tree[threadIdx.x] += tree[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (q & 1)
+                out[q >> 1].i = tree[0];
+            else
+                out[q >> 1].r = tree[0];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void state_init(KState *st, double beta) {
+    st->beta = beta;
+    st->scale = (beta > 0.0) ? 1.0 / beta : 0.0;
+    st->kk = 0;
+    st->breakdown = 0;
+    st->nonfinite = !(beta == beta && beta < 1e300);
+    for (int j = 0; j <= kMMax; ++j) st->g[j][0] = st->g[j][1] = 0.0;
+    st->g[0][0] = beta;
+}
+
+// Column k of the Hessenberg matrix: h (k+1 entries) and h_{k+1,k}; apply the
+// previous rotations, build the one annihilating h_{k+1,k}, rotate g.
+__device__ void givens_column(KState *st, int k, const D2 *h, double hk1) {
+    double cr[kMMax + 1][2];
+    for (int j = 0; j <= k; ++j) {
+        cr[j][0] = h[j].r;
+        cr[j][1] = h[j].i;
+    }
+    for (int j = 0; j < k; ++j) {
+        const double c = st->cs[j], sr = st->sn[j][0], si = st->sn[j][1];
+        const double ar = cr[j][0], ai = cr[j][1], br = cr[j + 1][0], bi = cr[j + 1][1];
+        // [c s; -conj(s) c] [a; b]
+        cr[j][0] = c * ar + (sr * br - si * bi);
+        cr[j][1] = c * ai + (sr * bi + si * br);
+        cr[j + 1][0] = -(sr * ar + si * ai) + c * br;
+        cr[j + 1][1] = -(sr * ai - si * ar) + c * bi;
+    }
+    const double ar = cr[k][0], ai = cr[k][1];
+    const double aa = sqrt(ar * ar + ai * ai);
+    const double rr = sqrt(aa * aa + hk1 * hk1);
+    double c, sr, si;
+    if (rr == 0.0) {
+        c = 1.0; sr = 0.0; si = 0.0;
+    } else if (aa == 0.0) {
+        c = 0.0; sr = 1.0; si = 0.0;
+    } else {
+        c = aa / rr;
+        sr = (ar / aa) * hk1 / rr;
+        si = (ai / aa) * hk1 / rr;
+    }
+    st->cs[k] = c;
+    st->sn[k][0] = sr;
+    st->sn[k][1] = si;
+    cr[k][0] = c * ar + sr * hk1;
+    cr[k][1] = c * ai + si * hk1;
+    for (int j = 0; j <= k; ++j) {
+        st->H[j][k][0] = cr[j][0];
+        st->H[j][k][1] = cr[j][1];
+    }
+    const double gr = st->g[k][0], gi = st->g[k][1];
+    st->g[k + 1][0] = -(sr * gr + si * gi);
+    st->g[k + 1][1] = -(sr * gi - si * gr);
+    st->g[k][0] = c * gr;
+    st->g[k][1] = c * gi;
+    st->kk = k + 1;
+    st->hk1 = hk1;
+    const bool ok = hk1 > kBreakdown * st->beta;
+    st->scale = ok ? 1.0 / hk1 : 0.0;
+    if (!ok) st->breakdown = 1;
+    if (!(hk1 == hk1) || !(st->g[k + 1][0] == st->g[k + 1][0])) st->nonfinite = 1;
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename T, int NV>
+struct Ptrs {
+    const T *v[NV > 0 ? NV : 1];
+};
+
+// sums conj(V_j) w (j < NV) and optionally ||w||^2
+template <typename T, int NV, bool NORM, int EPI>
+__global__ void __launch_bounds__(256) k_dots(Ptrs<T, NV> P, const T *__restrict__ w, long long n, KState *st,
+                                             double *out, RedBuf rb) {
+    constexpr int NS0 = NV + (NORM ? 1 : 0);
+    constexpr int NS = NS0 > 0 ? NS0 : 1;
+    D2 acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = {0, 0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const T wi = w[i];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] = acc[j] + cdot(P.v[j][i], wi);
+        if (NORM) acc[NV] = acc[NV] + D2{(double)wi.re * wi.re + (double)wi.im * wi.im, 0.0};
+    }
+    if (!reduce_partials<NS>(acc, rb)) return;
+    __shared__ D2 tot[kSlots];
+    sum_partials<NS>(rb, tot);
+    if (threadIdx.x == 0) {
+        if (EPI == EPI_STORE) {
+            for (int s = 0; s < NS; ++s) {
+                out[2 * s] = tot[s].r;
+                out[2 * s + 1] = tot[s].i;
+            }
+        } else if (EPI == EPI_ARNOLDI1) {
+            for (int j = 0; j < NV; ++j) {
+                st->h1[j][0] = tot[j].r;
+                st->h1[j][1] = tot[j].i;
+            }
+        } else if (EPI == EPI_NORM_INIT) {
+            state_init(st, sqrt(tot[NS - 1].r));
+        }
+        *rb.counter = 0u;
+    }
+}
+
+// w <- w - sum_j h1_j V_j; then conj(V_j) w and ||w||^2; Givens update of column NV-1
+template <typename T, int NV>
+__global__ void __launch_bounds__(256) k_axpy_dots(Ptrs<T, NV> P, T *__restrict__ w, long long n, KState *st,
+                                                  RedBuf rb) {
+    __shared__ double hs[NV][2];
+    if (threadIdx.x < NV) {
+        hs[threadIdx.x][0] = st->h1[threadIdx.x][0];
+        hs[threadIdx.x][1] = st->h1[threadIdx.x][1];
+    }
+    __syncthreads();
+    real_of<T> hr[NV], hi[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        hr[j] = (real_of<T>)hs[j][0];
+        hi[j] = (real_of<T>)hs[j][1];
+    }
+    D2 acc[NV + 1];
+#pragma unroll
+    for (int s = 0; s <= NV; ++s) acc[s] = {0, 0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        T v[NV];
+        T wi = w[i];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            v[j] = P.v[j][i];
+            wi.re -= hr[j] * v[j].re - hi[j] * v[j].im;
+            wi.im -= hr[j] * v[j].im + hi[j] * v[j].re;
+        }
+        w[i] = wi;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] = acc[j] + cdot(v[j], wi);
+        acc[NV] = acc[NV] + D2{(double)wi.re * wi.re + (double)wi.im * wi.im, 0.0};
+    }
+    if (!reduce_partials<NV + 1>(acc, rb)) return;
+    __shared__ D2 tot[kSlots];
+    sum_partials<NV + 1>(rb, tot);
+    if (threadIdx.x == 0) {
+        D2 h[NV];
+        double c2 = 0.0;
+        for (int j = 0; j < NV; ++j) {
+            st->h2[j][0] = tot[j].r;
+            st->h2[j][1] = tot[j].i;
+            h[j] = {st->h1[j][0] + tot[j].r, st->h1[j][1] + tot[j].i};
+            c2 += tot[j].r * tot[j].r + tot[j].i * tot[j].i;
+        }
+        // ||w - V h2||^2 = ||w||^2 - ||h2||^2 for orthonormal V
+        const double hk1 = sqrt(fmax(tot[NV].r - c2, 0.0));
+        givens_column(st, NV - 1, h, hk1);
+        *rb.counter = 0u;
+    }
+}
+
+// w <- (w - sum_j h2_j V_j) * scale
+template <typename T, int NV>
+__global__ void __launch_bounds__(256) k_axpy_scale(Ptrs<T, NV> P, T *__restrict__ w, long long n, const KState *st) {
+    __shared__ double hs[NV + 1][2];
+    if (threadIdx.x < NV) {
+        hs[threadIdx.x][0] = st->h2[threadIdx.x][0];
+        hs[threadIdx.x][1] = st->h2[threadIdx.x][1];
+    }
+    if (threadIdx.x == 0) hs[NV][0] = st->scale;
+    __syncthreads();
+    real_of<T> hr[NV], hi[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        hr[j] = (real_of<T>)hs[j][0];
+        hi[j] = (real_of<T>)hs[j][1];
+    }
+    const real_of<T> sc = (real_of<T>)hs[NV][0];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        T wi = w[i];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const T v = P.v[j][i];
+            wi.re -= hr[j] * v.re - hi[j] * v.im;
+            wi.im -= hr[j] * v.im + hi[j] * v.re;
+        }
+        wi.re *= sc;
+        wi.im *= sc;
+        w[i] = wi;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scale(const T *__restrict__ x, T *__restrict__ y, long long n,
+                                              const KState *st) {
+    const real_of<T> sc = (real_of<T>)st->scale;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        T v = x[i];
+        v.re *= sc;
+        v.im *= sc;
+        y[i] = v;
+    }
+}
+
+// x (+)= sum_j y_j Z_j, y by back substitution R y = g (guarded zero pivots) or
+// taken from st->y
+template <typename TX, typename TZ, int NV>
+__global__ void __launch_bounds__(256) k_combine(TX *__restrict__ x, Ptrs<TZ, NV> Zp, long long n, const KState *st,
+                                                int from_backsolve, int overwrite) {
+    __shared__ double ys[NV][2];
+    if (threadIdx.x == 0) {
+        if (from_backsolve) {
+            const int kk = st->kk < NV ? st->kk : NV;
+            for (int j = kk; j < NV; ++j) ys[j][0] = ys[j][1] = 0.0;
+            for (int i = kk - 1; i >= 0; --i) {
+                double sr = st->g[i][0], si = st->g[i][1];
+                for (int j = i + 1; j < kk; ++j) {
+                    const double hr = st->H[i][j][0], hi = st->H[i][j][1];
+                    sr -= hr * ys[j][0] - hi * ys[j][1];
+                    si -= hr * ys[j][1] + hi * ys[j][0];
+                }
+                const double dr = st->H[i][i][0], di = st->H[i][i][1];
+                const double d2 = dr * dr + di * di;
+                if (d2 == 0.0) {
+                    ys[i][0] = ys[i][1] = 0.0;
+                } else {
+                    ys[i][0] = (sr * dr + si * di) / d2;
+                    ys[i][1] = (si * dr - sr * di) / d2;
+                }
+            }
+        } else {
+            for (int j = 0; j < NV; ++j) {
+                ys[j][0] = st->y[j][0];
+                ys[j][1] = st->y[j][1];
+            }
+        }
+    }
+    __syncthreads();
+    real_of<TX> yr[NV], yi[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        yr[j] = (real_of<TX>)ys[j][0];
+        yi[j] = (real_of<TX>)ys[j][1];
+    }
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        TX acc;
+        if (overwrite) {
+            acc.re = 0;
+            acc.im = 0;
+        } else {
+            acc = x[i];
+        }
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const TZ z = Zp.v[j][i];
+            const real_of<TX> zr = (real_of<TX>)z.re, zi = (real_of<TX>)z.im;
+            acc.re += yr[j] * zr - yi[j] * zi;
+            acc.im += yr[j] * zi + yi[j] * zr;
+        }
+        x[i] = acc;
+    }
+}
+
+// Gram matrix G_ij = <P_i, P_j> (i <= j) of the s-step basis P_0..P_{NP-1}, then
+// the least-squares coefficients y of min ||P_0 - [P_1..P_{NP-1}] y|| from the
+// normal equations by Cholesky (truncated at a vanishing pivot).
+template <typename T, int NP>
+__global__ void __launch_bounds__(256) k_gram(Ptrs<T, NP> P, long long n, KState *st, RedBuf rb) {
+    constexpr int NS = NP * (NP + 1) / 2;
+    D2 acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = {0, 0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        T v[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) v[a] = P.v[a][i];
+        int s = 0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a)
+#pragma unroll
+            for (int b = a; b < NP; ++b) {
+                acc[s] = acc[s] + cdot(v[a], v[b]);
+                ++s;
+            }
+    }
+    if (!reduce_partials<NS>(acc, rb)) return;
+    __shared__ D2 tot[kSlots];
+    sum_partials<NS>(rb, tot);
+    if (threadIdx.x == 0) {
+        constexpr int m = NP - 1;
+        double G[NP][NP][2];
+        int s = 0;
+        for (int a = 0; a < NP; ++a)
+            for (int b = a; b < NP; ++b) {
+                G[a][b][0] = tot[s].r;
+                G[a][b][1] = tot[s].i;
+                G[b][a][0] = tot[s].r;
+                G[b][a][1] = -tot[s].i;
+                ++s;
+            }
+        double Lr[m][m], Li[m][m];
+        int rank = m;
+        for (int j = 0; j < m && rank == m; ++j) {
+            double d = G[j + 1][j + 1][0];
+            for (int k = 0; k < j; ++k) d -= Lr[j][k] * Lr[j][k] + Li[j][k] * Li[j][k];
+            if (!(d > 1e-24 * G[j + 1][j + 1][0])) {
+                rank = j;
+                break;
+            }
+            const double ljj = sqrt(d);
+            Lr[j][j] = ljj;
+            Li[j][j] = 0.0;
+            for (int i = j + 1; i < m; ++i) {
+                double ar = G[i + 1][j + 1][0], ai = G[i + 1][j + 1][1];
+                for (int k = 0; k < j; ++k) {   // - L_ik conj(L_jk)
+                    ar -= Lr[i][k] * Lr[j][k] + Li[i][k] * Li[j][k];
+                    ai -= Li[i][k] * Lr[j][k] - Lr[i][k] * Li[j][k];
+                }
+                Lr[i][j] = ar / ljj;
+                Li[i][j] = ai / ljj;
+            }
+        }
+        double ur[m], ui[m];
+        for (int i = 0; i < rank; ++i) {   // L u = rhs, rhs_i = <P_{i+1}, P_0>
+            double ar = G[i + 1][0][0], ai = G[i + 1][0][1];
+            for (int k = 0; k < i; ++k) {
+                ar -= Lr[i][k] * ur[k] - Li[i][k] * ui[k];
+                ai -= Lr[i][k] * ui[k] + Li[i][k] * ur[k];
+            }
+            ur[i] = ar / Lr[i][i];
+            ui[i] = ai / Lr[i][i];
+        }
+        for (int j = 0; j < kMMax; ++j) st->y[j][0] = st->y[j][1] = 0.0;
+        for (int i = rank - 1; i >= 0; --i) {   // L^H y = u
+            double ar = ur[i], ai = ui[i];
+            for (int k = i + 1; k < rank; ++k) {   // - conj(L_ki) y_k
+                ar -= Lr[k][i] * st->y[k][0] + Li[k][i] * st->y[k][1];
+                ai -= Lr[k][i] * st->y[k][1] - Li[k][i] * st->y[k][0];
+            }
+            st->y[i][0] = ar / Lr[i][i];
+            st->y[i][1] = ai / Lr[i][i];
+        }
+        if (!(G[0][0][0] == G[0][0][0]) || !(G[0][0][0] < 1e300)) st->nonfinite = 1;
+        *rb.counter = 0u;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_zero(T *x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        T z;
+        z.re = 0;
+        z.im = 0;
+        x[i] = z;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_add(const T *__restrict__ x, T *__restrict__ y, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        T v = y[i];
+        const T a = x[i];
+        v.re += a.re;
+        v.im += a.im;
+        y[i] = v;
+    }
+}
+
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_convert(const TI *__restrict__ x, TO *__restrict__ y, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        TO o;
+        o.re = (real_of<TO>)x[i].re;
+        o.im = (real_of<TO>)x[i].im;
+        y[i] = o;
+    }
+}
+
+// velocity on the nodes of one level: nearest physical value in the PML
+// (Sec. 2.1), sampled at every stride-th fine node (Sec. 3.1)
+__global__ void __launch_bounds__(256) k_extend_velocity(const float *__restrict__ phys, int nxp, int nyp, int nzp,
+                                                        int n_pml, int stride, Geom g, float *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.nn; i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % g.sx);
+        const int y = (int)((i / g.sx) % (g.n[1] + 1));
+        const int z = (int)(i / g.sy);
+        const int px = min(max(x * stride - n_pml, 0), nxp);
+        const int py = min(max(y * stride - n_pml, 0), nyp);
+        const int pz = min(max(z * stride - n_pml, 0), nzp);
+        out[i] = phys[((long long)pz * (nyp + 1) + py) * (nxp + 1) + px];
+    }
+}
+
+// min, max and the count of non-finite values of the velocity
+__global__ void __launch_bounds__(256) k_velocity_check(const float *__restrict__ v, long long n, RedBuf rb,
+                                                       double *out) {
+    double mn = 1e300, mx = -1e300, bad = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float c = v[i];
+        if (!(c == c) || c > 3.0e38f || c < -3.0e38f) {
+            bad += 1;
+        } else {
+            mn = fmin(mn, (double)c);
+            mx = fmax(mx, (double)c);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, off, 64));
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+        bad += __shfl_xor(bad, off, 64);
+    }
+    __shared__ double red[4][3];
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[w][0] = mn;
+        red[w][1] = mx;
+        red[w][2] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            red[0][0] = fmin(red[0][0], red[k][0]);
+            red[0][1] = fmax(red[0][1], red[k][1]);
+            red[0][2] += red[k][2];
+        }
+        rb.partials[3 * blockIdx.x + 0] = red[0][0];
+        rb.partials[3 * blockIdx.x + 1] = red[0][1];
+        rb.partials[3 * blockIdx.x + 2] = red[0][2];
+        __threadfence();
+        last = (atomicAdd(rb.counter, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        double a = 1e300, b = -1e300, c = 0;
+        for (unsigned k = 0; k < gridDim.x; ++k) {
+            a = fmin(a, __hip_atomic_load(rb.partials + 3 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            b = fmax(b, __hip_atomic_load(rb.partials + 3 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            c += __hip_atomic_load(rb.partials + 3 * k + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        out[0] = a;
+        out[1] = b;
+        out[2] = c;
+        *rb.counter = 0u;
+    }
+}
+
+int red_blocks(long long n) {
+    long long b = (n + 1023) / 1024;
+    if (b < 1) b = 1;
+    if (b > kRedBlocks) b = kRedBlocks;
+    return (int)b;
+}
+
+int stream_blocks(long long n) {
+    long long b = (n + 1023) / 1024;
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (int)b;
+}
+
+template <typename T, int NV>
+Ptrs<T, NV> pack(const T *const *V) {
+    Ptrs<T, NV> p{};
+    for (int j = 0; j < NV; ++j) p.v[j] = V[j];
+    return p;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long long n, int epi, KState *st, int k,
+                       double *out, const RedBuf &rb, hipStream_t s) {
+    (void)k;
+    const int nb = red_blocks(n);
+#define HELM_DOTS(NV)                                                                                               \
+    case NV:                                                                                                        \
+        if (norm) {                                                                                                 \
+            if (epi == EPI_STORE)                                                                                   \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_STORE>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, n, \
+                                   st, out, rb);                                                                    \
+            else if (epi == EPI_NORM_INIT)                                                                          \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_NORM_INIT>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), \
+                                   w, n, st, out, rb);                                                              \
+            else                                                                                                    \
+                return hipErrorInvalidValue;                                                                        \
+        } else {                                                                                                    \
+            if (epi == EPI_STORE)                                                                                   \
+                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_STORE>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, \
+                                   n, st, out, rb);                                                                 \
+            else if (epi == EPI_ARNOLDI1)                                                                           \
+                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_ARNOLDI1>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), \
+                                   w, n, st, out, rb);                                                              \
+            else                                                                                                    \
+                return hipErrorInvalidValue;                                                                        \
+        }                                                                                                           \
+        break;
+    switch (nv) {
+        HELM_DOTS(0) HELM_DOTS(1) HELM_DOTS(2) HELM_DOTS(3) HELM_DOTS(4) HELM_DOTS(5) HELM_DOTS(6) HELM_DOTS(7)
+        HELM_DOTS(8) HELM_DOTS(9) HELM_DOTS(10) HELM_DOTS(11) HELM_DOTS(12)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef HELM_DOTS
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpy_dots(const T *const *V, int nv, T *w, long long n, KState *st, const RedBuf &rb,
+                            hipStream_t s) {
+    const int nb = red_blocks(n);
+#define HELM_AD(NV) \
+    case NV: hipLaunchKernelGGL((k_axpy_dots<T, NV>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, n, st, rb); break;
+    switch (nv) {
+        HELM_AD(1) HELM_AD(2) HELM_AD(3) HELM_AD(4) HELM_AD(5) HELM_AD(6) HELM_AD(7) HELM_AD(8) HELM_AD(9)
+        HELM_AD(10) HELM_AD(11) HELM_AD(12)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef HELM_AD
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KState *st, hipStream_t s) {
+    const int nb = stream_blocks(n);
+#define HELM_AS(NV) \
+    case NV: hipLaunchKernelGGL((k_axpy_scale<T, NV>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, n, st); break;
+    switch (nv) {
+        HELM_AS(1) HELM_AS(2) HELM_AS(3) HELM_AS(4) HELM_AS(5) HELM_AS(6) HELM_AS(7) HELM_AS(8) HELM_AS(9)
+        HELM_AS(10) HELM_AS(11) HELM_AS(12)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef HELM_AS
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale(const T *x, T *y, long long n, const KState *st, hipStream_t s) {
+    hipLaunchKernelGGL((k_scale<T>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n, st);
+    return hipGetLastError();
+}
+
+template <typename TX, typename TZ>
+hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, const KState *st, bool from_backsolve,
+                          bool overwrite, hipStream_t s) {
+    const int nb = stream_blocks(n);
+#define HELM_CB(NV)                                                                                            \
+    case NV:                                                                                                   \
+        hipLaunchKernelGGL((k_combine<TX, TZ, NV>), dim3(nb), dim3(256), 0, s, x, pack<TZ, NV>(Z), n, st,       \
+                           (int)from_backsolve, (int)overwrite);                                               \
+        break;
+    switch (nz) {
+        HELM_CB(1) HELM_CB(2) HELM_CB(3) HELM_CB(4) HELM_CB(5) HELM_CB(6) HELM_CB(7) HELM_CB(8) HELM_CB(9)
+        HELM_CB(10) HELM_CB(11) HELM_CB(12)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef HELM_CB
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gram(const T *const *P, int np, long long n, KState *st, const RedBuf &rb, hipStream_t s) {
+    const int nb = red_blocks(n);
+#define HELM_GR(NP) \
+    case NP: hipLaunchKernelGGL((k_gram<T, NP>), dim3(nb), dim3(256), 0, s, pack<T, NP>(P), n, st, rb); break;
+    switch (np) {
+        HELM_GR(2) HELM_GR(3) HELM_GR(4) HELM_GR(5) HELM_GR(6) HELM_GR(7) HELM_GR(8) HELM_GR(9)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef HELM_GR
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_zero(T *x, long long n, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(stream_blocks(n)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_add(const T *x, T *y, long long n, hipStream_t s) {
+    hipLaunchKernelGGL((k_add<T>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t launch_convert(const TI *x, TO *y, long long n, hipStream_t s) {
+    hipLaunchKernelGGL((k_convert<TI, TO>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_extend_velocity(const float *phys, const int nphys[3], int n_pml, int stride, const Geom &g,
+                                  float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_extend_velocity, dim3(stream_blocks(g.nn)), dim3(256), 0, s, phys, nphys[0], nphys[1],
+                       nphys[2], n_pml, stride, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_velocity_check, dim3(red_blocks(n)), dim3(256), 0, s, v, n, rb, out);
+    return hipGetLastError();
+}
+
+#define HELM_INST(T)                                                                                              \
+    template hipError_t launch_dots<T>(const T *const *, int, const T *, bool, long long, int, KState *, int,     \
+                                       double *, const RedBuf &, hipStream_t);                                    \
+    template hipError_t launch_axpy_dots<T>(const T *const *, int, T *, long long, KState *, const RedBuf &,      \
+                                            hipStream_t);                                                         \
+    template hipError_t launch_axpy_scale<T>(const T *const *, int, T *, long long, KState *, hipStream_t);       \
+    template hipError_t launch_scale<T>(const T *, T *, long long, const KState *, hipStream_t);                  \
+    template hipError_t launch_gram<T>(const T *const *, int, long long, KState *, const RedBuf &, hipStream_t); \
+    template hipError_t launch_fill_zero<T>(T *, long long, hipStream_t);                                      \
+    template hipError_t launch_add<T>(const T *, T *, long long, hipStream_t);
+HELM_INST(c32)
+HELM_INST(c64)
+#undef HELM_INST
+template hipError_t launch_combine<c32, c32>(c32 *, const c32 *const *, int, long long, const KState *, bool, bool,
+                                             hipStream_t);
+template hipError_t launch_combine<c64, c64>(c64 *, const c64 *const *, int, long long, const KState *, bool, bool,
+                                             hipStream_t);
+template hipError_t launch_combine<c64, c32>(c64 *, const c32 *const *, int, long long, const KState *, bool, bool,
+                                             hipStream_t);
+template hipError_t launch_convert<c32, c64>(const c32 *, c64 *, long long, hipStream_t);
+template hipError_t launch_convert<c64, c32>(const c64 *, c32 *, long long, hipStream_t);
+template hipError_t launch_convert<c32, c32>(const c32 *, c32 *, long long, hipStream_t);
+template hipError_t launch_convert<c64, c64>(const c64 *, c64 *, long long, hipStream_t);
+
+}  // namespace helm

@@ -1,0 +1,122 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/helm.h declares, fills the default options, sizes the workspace and
+rejects invalid arguments on the host before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2608_22946_amd import helm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(helm._LIB_PATH):
+        from paper_2608_22946_amd import build
+        build.build()
+    return helm.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "helm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(helm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(helm.EXPORTED)
+
+
+def test_default_options_match_paper_protocol(L):
+    o = helm.default_options()
+    assert o.struct_size == ctypes.sizeof(helm.HelmOptions)
+    assert (o.sigma, o.omega_h, o.omega_2h, o.omega_4h, o.gamma_max) == (0.9, 0.8, 0.8, 0.2, 1.119058)
+    assert (o.nJ_h, o.nJ_2h, o.nJ_4h, o.m_h, o.c_2h, o.m_2h, o.m_4h, o.m_out) == (2, 2, 2, 2, 2, 10, 4, 5)
+
+
+def _opts(**kw):
+    o = helm.default_options()
+    o.iofd_K = 40
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ws(L, dims, n_pml, o):
+    b = ctypes.c_size_t(0)
+    rc = L.helm_workspace_size(*dims, n_pml, ctypes.byref(o), ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_size_scales_with_grid_and_precision(L):
+    rc, b32 = _ws(L, (56, 56, 56), 4, _opts(precision=helm.FP32))
+    assert rc == 0
+    rc, b64 = _ws(L, (56, 56, 56), 4, _opts(precision=helm.FP64))
+    assert rc == 0
+    n0 = 65 ** 3
+    # at least the outer basis (11), smoother (5) and FP64 x, b at the fine level
+    assert b32 >= n0 * (16 * 8 + 2 * 16)
+    assert b64 > b32
+    rc, big = _ws(L, (112, 112, 112), 8, _opts(precision=helm.FP32))
+    assert 7.0 < big / b32 < 9.0
+
+
+@pytest.mark.parametrize("dims,n_pml", [((10, 12, 12), 0), ((12, 12, 12), -1), ((0, 12, 12), 2), ((2, 2, 2), 1),
+                                        ((4094, 8, 8), 2)])
+def test_bad_dims_rejected(L, dims, n_pml):
+    rc, _ = _ws(L, dims, n_pml, _opts())
+    assert rc == helm.HELM_OK - 1   # HELM_EINVAL
+    assert L.helm_last_error(None)
+
+
+@pytest.mark.parametrize("field,value", [("m_out", 0), ("m_2h", 13), ("m_4h", 9), ("nJ_h", 0), ("c_2h", 0),
+                                         ("iofd_K", 0), ("omega_2h", -0.1), ("struct_size", 8), ("precision", 7)])
+def test_bad_options_rejected(L, field, value):
+    rc, _ = _ws(L, (24, 24, 24), 4, _opts(**{field: value}))
+    assert rc == -1
+
+
+def test_setup_validates_before_device_work(L):
+    """Every failure below is decided on the host; none touches the GPU."""
+    tab = helm.table_flat(helm.load_table())
+    o = _opts()
+    o.iofd_table = tab.ctypes.data
+    out = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)
+    # NULL velocity
+    assert L.helm_setup(None, 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o), dummy, 1 << 30, ctypes.byref(out)) == -1
+    # bad h / omega
+    assert L.helm_setup(dummy, 24, 24, 24, -1.0, 1.0, 4, ctypes.byref(o), dummy, 1 << 30, ctypes.byref(out)) == -1
+    assert L.helm_setup(dummy, 24, 24, 24, 10.0, float("nan"), 4, ctypes.byref(o), dummy, 1 << 30,
+                        ctypes.byref(out)) == -1
+    # missing table
+    o2 = _opts()
+    assert L.helm_setup(dummy, 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o2), dummy, 1 << 30, ctypes.byref(out)) == -1
+    # non-finite table entry
+    bad = tab.copy()
+    bad[5] = np.nan
+    o3 = _opts()
+    o3.iofd_table = bad.ctypes.data
+    assert L.helm_setup(dummy, 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o3), dummy, 1 << 30, ctypes.byref(out)) == -1
+    # workspace too small, and misaligned
+    assert L.helm_setup(dummy, 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o), dummy, 100, ctypes.byref(out)) == -2
+    assert L.helm_setup(ctypes.c_void_p(0x1001), 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o), ctypes.c_void_p(0x1008),
+                        1 << 40, ctypes.byref(out)) == -2
+    assert b"workspace" in L.helm_last_error(None)
+
+
+def test_calls_on_null_hierarchy(L):
+    its = np.zeros(1, np.int32)
+    rel = np.zeros(1)
+    assert L.helm_solve(None, ctypes.c_void_p(8), 1, 1e-6, ctypes.c_void_p(16), its.ctypes.data, rel.ctypes.data) == -1
+    assert L.helm_apply(None, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(16)) == -1
+    assert L.helm_grad(None, None, 1, 1e-6, None) == -5
+    L.helm_destroy(None)
