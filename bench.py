@@ -1,0 +1,211 @@
+"""Benchmark: time to a true relative residual of 1e-6 per right-hand side on
+one MI355X, plus the fine-level stencil-apply bandwidth against the HBM peak.
+
+Workload (one "step" = one full solve, all steps of the hot path):
+  320^3 physical intervals + 16 PML cells per face (352^3 total, 44.0M nodes),
+  h = 10 m, velocity 2000 m/s x (1 + 0.25 g), g a seeded Gaussian random field
+  (correlation length 20 cells, max|g| = 1), clipped to [1500, 3000] m/s,
+  omega for 6 points per wavelength at the minimum velocity, one point source
+  h^-3 at a seeded node at least 6 cells inside the physical box, FP32 complex,
+  outer tolerance 1e-6 (true residual recomputed in FP64), fixed solver
+  configuration of the paper's performance table.
+
+Prints one JSON line.  `python bench.py --gpus 1 --steps K --warmup W`.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_PHYS, N_PML, H, TOL, SEED = 320, 16, 10.0, 1e-6, 2
+COUNTER_FILE = os.path.join(ROOT, "profiles", "stencil_apply_352_fp32_counters.txt")
+STENCIL_SRC = os.path.join(ROOT, "paper_2608_22946_amd", "csrc", "stencil.hip")
+
+
+def workload():
+    from workloads import grf_velocity, point_source
+    from workloads.configs import omega_for_ppw
+    vel = grf_velocity(N_PHYS, N_PHYS, N_PHYS, seed=SEED)
+    omega = omega_for_ppw(float(vel.min()), H)
+    N = N_PHYS + 2 * N_PML
+    rng = np.random.default_rng(SEED)
+    src = tuple(int(v) for v in rng.integers(N_PML + 6, N_PML + N_PHYS - 6, 3))
+    f = point_source((N, N, N), src, H, dtype=np.complex64)
+    return vel, omega, f, src
+
+
+def stencil_hash():
+    with open(STENCIL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def recorded_traffic(nodes):
+    """HBM bytes per apply from the committed counter summary, if it was taken
+    on the current stencil source; else None."""
+    if not os.path.exists(COUNTER_FILE):
+        return None
+    vals = {}
+    for line in open(COUNTER_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("stencil_sha") != stencil_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_apply"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(vel, omega, table, gpu_pc_calls):
+    """The FP64 reference checker on the host cores: one preconditioner
+    application (Algorithm 1) on the full workload, scaled to seconds per
+    right-hand side by the GPU run's preconditioner-call count."""
+    from oracle.oracle import Hierarchy as OracleHierarchy
+    from workloads import random_complex
+    O = OracleHierarchy(vel, H, omega, N_PML, table)
+    N = N_PHYS + 2 * N_PML
+    r = random_complex((N, N, N), 7)
+    r /= np.linalg.norm(r)
+    t0 = time.perf_counter()
+    O.precond(r)
+    t_pc = time.perf_counter() - t0
+    O.close()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": t_pc * gpu_pc_calls, "unit": "s per RHS (extrapolated)", "cores": cores, "kind": "oracle",
+            "sample": f"one FP64 preconditioner application (Algorithm 1) on the full 352^3 workload took "
+                      f"{t_pc:.2f} s; scaled by the GPU solve's {gpu_pc_calls} preconditioner calls"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-apply", action="store_true",
+                    help="only run the fine-level apply loop and a plain copy of the same size (for counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see the sharding design).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import load_iofd_table
+
+    t_gen = time.perf_counter()
+    vel, omega, f_np, src = workload()
+    table = load_iofd_table()
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Hh = helm.Hierarchy(torch.from_numpy(vel), H, omega, N_PML, precision="fp32", table=table, device=dev)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    nodes = [int(np.prod(Hh.shape(l))) for l in range(3)]
+    f = torch.from_numpy(f_np).to(dev)
+
+    # ---- fine-level stencil apply: algorithmic bytes / average kernel time (HIP events) ----
+    x = torch.randn(Hh.shape(0), dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        Hh.apply(0, helm.OP_A, x, out=y)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.apply_reps):
+        Hh.apply(0, helm.OP_A, x, out=y)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_apply = ev0.elapsed_time(ev1) / 1e3 / args.apply_reps
+    alg_bytes = 20.0 * nodes[0]                        # 8 B in + 8 B out + 4 B velocity per node
+    achieved = alg_bytes / t_apply / 1e9
+    if args.profile_apply:
+        z = torch.empty_like(x)
+        for _ in range(args.apply_reps):
+            z.copy_(x)                                   # plain copy of known size, for counter calibration
+        torch.cuda.synchronize()
+        print(json.dumps({"apply_ms": t_apply * 1e3, "apply_GBs": achieved, "nodes": nodes[0],
+                          "copy_bytes_each_way": x.numel() * 8, "stencil_sha": stencil_hash()}))
+        return
+    level_gbs = {}
+    for lvl in (1, 2):
+        xl = torch.randn(Hh.shape(lvl), dtype=torch.complex64, device=dev)
+        yl = torch.empty_like(xl)
+        Hh.apply(lvl, helm.OP_B, xl, out=yl)
+        ev0.record(stream)
+        for _ in range(args.apply_reps):
+            Hh.apply(lvl, helm.OP_B, xl, out=yl)
+        ev1.record(stream)
+        ev1.synchronize()
+        tl = ev0.elapsed_time(ev1) / 1e3 / args.apply_reps
+        level_gbs[f"level{lvl}_B_apply_GBs_cache_resident"] = round(20.0 * nodes[lvl] / tl / 1e9, 1)
+    del x, y
+
+    # ---- solves: warmup, then exactly K timed steps ----
+    u = torch.empty_like(f)
+    its = rel = None
+    for _ in range(args.warmup):
+        _, its, rel, rc = Hh.solve(f, TOL, out=u.unsqueeze(0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, its, rel, rc = Hh.solve(f, TOL, out=u.unsqueeze(0))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    ms_step = t_total / args.steps * 1e3
+    if rc != 0 or not rel <= TOL:
+        print(json.dumps({"error": "solve did not reach the tolerance", "relres": rel, "iters": its}))
+        sys.exit(1)
+
+    traffic = recorded_traffic(nodes[0])
+    out = {
+        "metric": "time-to-rel.res 1e-6 per RHS + stencil-apply HBM GB/s vs peak",
+        "value": round(ms_step / 1e3, 4),
+        "unit": "s per RHS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grf-352-fp32: 320^3 + 16-cell PML, GRF velocity 2000 m/s +-25% (corr. 20 cells), "
+                               "6 ppw at c_min, 1 seeded point source, tol 1e-6",
+                   "grid_total": N_PHYS + 2 * N_PML, "n_pml": N_PML, "nodes_fine": nodes[0], "source": list(src),
+                   "tol": TOL, "precision": "fp32 (outer x, b and true residual in fp64)"},
+        "roofline": {"bound": "hbm", "kernel": "fine-level A_h apply (27-point IOFD, 352^3, fp32)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": round(t_apply * 1e3, 4)},
+        "pc_calls": int(its),
+        "relres": float(rel),
+        "solve_per_pc_ms": round(ms_step / max(int(its), 1), 2),
+        "setup_s": round(t_setup, 3),
+        **level_gbs,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(vel, omega, table, int(its))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

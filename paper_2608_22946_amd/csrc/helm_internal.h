@@ -167,4 +167,29 @@ hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, 
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Cross-block completion ticket without device-wide cache maintenance.
+// Partial results are written with agent-scope atomic stores (write-through
+// to the device coherence point, past the per-XCD L2), every store is
+// waited for (s_waitcnt) before the block takes a ticket with an agent-scope
+// atomic add, and the last block reads the partials with agent-scope atomic
+// loads.  A __threadfence() here would write back and invalidate the whole
+// L2 of the XCD in every block, evicting the operands other blocks stream.
+__device__ __forceinline__ void partial_store(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double partial_load(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_done() {
+    __builtin_amdgcn_s_waitcnt(0);          // vmcnt/expcnt/lgkmcnt = 0: this thread's stores are performed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// returns true in exactly one block: the last to arrive (call from one thread)
+__device__ __forceinline__ bool take_ticket(unsigned *counter, unsigned nblocks) {
+    return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1;
+}
+__device__ __forceinline__ void reset_ticket(unsigned *counter) {
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace helm

@@ -135,47 +135,54 @@ template <typename R>
 struct Plane {
     Z<R> p0, p1, p2;   // centre, 4 in-plane face neighbours, 4 in-plane corners
     Z<R> ea, eb;       // x/y stiffness partials (tensor form only)
+    Z<R> gc;           // right-hand side at the centre (residual / Jacobi modes)
+    float cc;          // velocity at the centre
 };
 
-template <typename R>
-struct Rows {
-    Z<R> a, b, c;      // rows y-1, y, y+1 at this lane's x
-};
-
-// in-plane partial sums of one z plane (x neighbours from adjacent lanes)
-template <typename R, bool XYI>
-__device__ __forceinline__ Plane<R> plane_partials(const Rows<R> &v, const Z<R> *wx, const Z<R> *wy) {
-    Plane<R> P;
-    Z<R> col = zadd(v.a, v.c);
-    if (XYI) {
-        P.p0 = v.b;
-        P.p1 = zadd(col, zadd(zleft(v.b), zright(v.b)));
+// In-plane partial sums of one z plane from the rows y-1 (a), y (b), y+1 (c)
+// at this lane's x; x neighbours come from the adjacent lanes.  XI / YI: the
+// x / y stretching of this wave is the identity (weights -1, 2, -1).
+template <typename R, bool XI, bool YI>
+__device__ __forceinline__ void plane_partials(Z<R> a, Z<R> b, Z<R> c, const Z<R> *wx, const Z<R> *wy,
+                                               Plane<R> &P) {
+    const Z<R> col = zadd(a, c);
+    const Z<R> bL = zleft(b), bR = zright(b);
+    P.p0 = b;
+    if (XI && YI) {
+        P.p1 = zadd(col, zadd(bL, bR));
         P.p2 = zadd(zleft(col), zright(col));
-        P.ea = P.eb = Z<R>{0, 0};
+        return;
+    }
+    const Z<R> aL = zleft(a), aR = zright(a), cL = zleft(c), cR = zright(c);
+    const Z<R> colL = zadd(aL, cL), colR = zadd(aR, cR);
+    const Z<R> rsm = zadd(aL, aR), rs0 = zadd(bL, bR), rsp = zadd(cL, cR);
+    P.p1 = zadd(col, rs0);
+    P.p2 = zadd(rsm, rsp);
+    Z<R> ea, eb;
+    if (XI) {            // -1, 2, -1 along x
+        ea = zsub(zscale((R)2, b), rs0);
+        eb = zsub(zscale((R)2, col), zadd(colL, colR));
     } else {
-        Z<R> aL = zleft(v.a), aR = zright(v.a), bL = zleft(v.b), bR = zright(v.b), cL = zleft(v.c),
-             cR = zright(v.c);
-        Z<R> colL = zadd(aL, cL), colR = zadd(aR, cR);
-        Z<R> rsm = zadd(aL, aR), rs0 = zadd(bL, bR), rsp = zadd(cL, cR);
-        P.p0 = v.b;
-        P.p1 = zadd(col, rs0);
-        P.p2 = zadd(rsm, rsp);
-        Z<R> ea = zmul(wx[0], bL);
-        ea = zfma(wx[1], v.b, ea);
+        ea = zmul(wx[0], bL);
+        ea = zfma(wx[1], b, ea);
         ea = zfma(wx[2], bR, ea);
-        ea = zfma(wy[0], v.a, ea);
-        ea = zfma(wy[1], v.b, ea);
-        ea = zfma(wy[2], v.c, ea);
-        Z<R> eb = zmul(wx[0], colL);
+        eb = zmul(wx[0], colL);
         eb = zfma(wx[1], col, eb);
         eb = zfma(wx[2], colR, eb);
+    }
+    if (YI) {            // -1, 2, -1 along y
+        ea = zadd(ea, zsub(zscale((R)2, b), col));
+        eb = zadd(eb, zsub(zscale((R)2, rs0), zadd(rsm, rsp)));
+    } else {
+        ea = zfma(wy[0], a, ea);
+        ea = zfma(wy[1], b, ea);
+        ea = zfma(wy[2], c, ea);
         eb = zfma(wy[0], rsm, eb);
         eb = zfma(wy[1], rs0, eb);
         eb = zfma(wy[2], rsp, eb);
-        P.ea = ea;
-        P.eb = eb;
     }
-    return P;
+    P.ea = ea;
+    P.eb = eb;
 }
 
 // ell^2 (H v) at the centre of plane "o" from planes m (z-1), o (z), p (z+1)
@@ -183,25 +190,36 @@ template <typename R, bool XYI, bool SHIFT>
 __device__ __forceinline__ Z<R> row_value(const LevelArgs<R> &L, const Coef<R> &cf, const Plane<R> &m,
                                           const Plane<R> &o, const Plane<R> &p, bool zint, const Z<R> *wz) {
     // shell sums S_m over the 1 / 6 / 12 / 8 neighbours
-    Z<R> S0 = o.p0;
-    Z<R> S1 = zadd(o.p1, zadd(m.p0, p.p0));
-    Z<R> S2 = zadd(o.p2, zadd(m.p1, p.p1));
-    Z<R> S3 = zadd(m.p2, p.p2);
+    const Z<R> S0 = o.p0;
+    const Z<R> S1 = zadd(o.p1, zadd(m.p0, p.p0));
+    const Z<R> S2 = zadd(o.p2, zadd(m.p1, p.p1));
+    const Z<R> S3 = zadd(m.p2, p.p2);
     const R a1 = cf.a1, a2 = cf.a2, a3 = cf.a3, a4 = cf.a4, a5 = cf.a5;
     const R q = (R)1 - a4 - a5;
-    const R mass0 = a1, mass1 = a2 * (R)(1.0 / 6), mass2 = a3 * (R)(1.0 / 12), mass3 = ((R)1 - a1 - a2 - a3) * (R)0.125;
-    Z<R> Mass = zscale(mass0, S0);
-    Mass = zadd(Mass, zscale(mass1, S1));
-    Mass = zadd(Mass, zscale(mass2, S2));
-    Mass = zadd(Mass, zscale(mass3, S3));
-    Z<R> St;
+    const R m0 = a1, m1 = a2 * (R)(1.0 / 6), m2 = a3 * (R)(1.0 / 12), m3 = ((R)1 - a1 - a2 - a3) * (R)0.125;
     if (XYI && zint) {
-        // eq. iofd-shell-coefficients, stiffness parts
-        St = zscale((R)6 * a4, S0);
-        St = zadd(St, zscale(a5 - a4, S1));
-        St = zadd(St, zscale((R)0.5 * (q - a5), S2));
-        St = zadd(St, zscale((R)-0.75 * q, S3));
-    } else {
+        // eq. iofd-shell-coefficients: C_m = stiffness_m - mu kappa^2 mass_m, then sum_m C_m S_m
+        const R k2 = cf.k2;
+        const R c0 = (R)6 * a4 - k2 * m0, c1 = (a5 - a4) - k2 * m1, c2 = (R)0.5 * (q - a5) - k2 * m2,
+                c3 = (R)-0.75 * q - k2 * m3;
+        Z<R> out;
+        out.r = c0 * S0.r + c1 * S1.r + c2 * S2.r + c3 * S3.r;
+        out.i = c0 * S0.i + c1 * S1.i + c2 * S2.i + c3 * S3.i;
+        if (SHIFT) {   // - i sigma kappa^2 sum_m mass_m S_m
+            const R sk = L.sigma * k2;
+            const R mr = m0 * S0.r + m1 * S1.r + m2 * S2.r + m3 * S3.r;
+            const R mi = m0 * S0.i + m1 * S1.i + m2 * S2.i + m3 * S3.i;
+            out.r += sk * mi;
+            out.i -= sk * mr;
+        }
+        return zscale(L.inv_ell2, out);
+    }
+    Z<R> Mass = zscale(m0, S0);
+    Mass = zadd(Mass, zscale(m1, S1));
+    Mass = zadd(Mass, zscale(m2, S2));
+    Mass = zadd(Mass, zscale(m3, S3));
+    Z<R> St;
+    {
         const R t0 = a4, t1 = a5 * (R)0.25, t2 = q * (R)0.25;
         Z<R> eam, ebm, eao, ebo, eap, ebp;
         if (XYI) {   // unit x/y stretching: Ea = 4 P0 - P1, Eb = 2 P1 - 2 P2
@@ -251,7 +269,8 @@ __device__ __forceinline__ void block_reduce_store(double v, double *dst) {
     if (w == 0 && l == 0) {
         double s = 0;
         for (int i = 0; i < kWavesY; ++i) s += red[i];
-        *dst = s;
+        partial_store(dst, s);
+        stores_done();
     }
 }
 
@@ -260,14 +279,11 @@ __device__ void norm_epilogue(const RedBuf &rb, int nblocks, KState *st) {
     __shared__ bool last;
     __shared__ double red[256];
     const int tid = threadIdx.x + 64 * threadIdx.y;
-    __threadfence();
-    if (tid == 0) last = (atomicAdd(rb.counter, 1u) == (unsigned)nblocks - 1);
+    if (tid == 0) last = take_ticket(rb.counter, nblocks);
     __syncthreads();
     if (!last) return;
-    __threadfence();
     double s = 0;
-    for (int b = tid; b < nblocks; b += 256)
-        s += __hip_atomic_load(rb.partials + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int b = tid; b < nblocks; b += 256) s += partial_load(rb.partials + b);
     red[tid] = s;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -283,128 +299,175 @@ __device__ void norm_epilogue(const RedBuf &rb, int nblocks, KState *st) {
         st->nonfinite = !(beta == beta && beta < 1e300);
         for (int j = 0; j <= kMMax; ++j) st->g[j][0] = st->g[j][1] = 0.0;
         st->g[0][0] = beta;
-        *rb.counter = 0u;
+        reset_ticket(rb.counter);
     }
 }
 
-template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM, bool XYI>
+template <typename T>
+__device__ __forceinline__ const T *plane_ptr(const T *base, long long plane_stride, int z) {
+    return base + (long long)z * plane_stride;
+}
+template <typename T>
+__device__ __forceinline__ T at_byte(const T *plane, unsigned off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(plane) + off);
+}
+
+// One wavefront: rows y-1, y, y+1 at 64 consecutive x, marching planes z0..z1-1.
+// Every load reads an in-bounds node (indices clamped to the grid) and
+// boundary / out-of-box values are masked to zero afterwards, so the loads
+// carry no branches; the per-lane byte offsets inside a plane are fixed and the
+// plane base is wave-uniform (scalar registers).
+template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM, bool XI, bool YI>
 __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, const TX *__restrict__ x,
                                       const TG *__restrict__ g, const TY *__restrict__ base, TY *__restrict__ y,
                                       R omegaJ, int xg, int yg, int z0, int z1, bool out_lane, double &nrm) {
+    constexpr bool JAC = (MODE == M_JAC2 || MODE == M_JAC2_ADD);
+    constexpr bool NEED_G = (MODE != M_APPLY);
     const bool x_int = (xg >= 1 && xg <= L.nx - 1);
-    const long long rowoff = (long long)yg * L.sx + xg;
-    Z<R> wx[3] = {{0, 0}, {0, 0}, {0, 0}}, wy[3] = {{0, 0}, {0, 0}, {0, 0}};
-    Z<R> wyc_m = {0, 0}, wyc_p = {0, 0};
-    if (x_int) {
-        const R *w = L.wx + 6 * xg;
-        wx[0] = {w[0], w[1]}; wx[1] = {w[2], w[3]}; wx[2] = {w[4], w[5]};
-    }
-    {
-        const R *w = L.wy + 6 * yg;
-        wy[0] = {w[0], w[1]}; wy[1] = {w[2], w[3]}; wy[2] = {w[4], w[5]};
-        if (MODE == M_JAC2 || MODE == M_JAC2_ADD) {
-            if (yg - 1 >= 1) wyc_m = {L.wy[6 * (yg - 1) + 2], L.wy[6 * (yg - 1) + 3]};
-            if (yg + 1 <= L.ny - 1) wyc_p = {L.wy[6 * (yg + 1) + 2], L.wy[6 * (yg + 1) + 3]};
-        }
-    }
+    const int xc = min(max(xg, 0), L.nx);
+    const int ym = max(yg - 1, 0), yp = min(yg + 1, L.ny);
+    const unsigned e0 = (unsigned)(yg * (int)L.sx + xc), em = (unsigned)(ym * (int)L.sx + xc),
+                   ep = (unsigned)(yp * (int)L.sx + xc);
+    const unsigned bx0 = e0 * sizeof(TX), bxm = em * sizeof(TX), bxp = ep * sizeof(TX);
+    const unsigned bg0 = e0 * sizeof(TG), bgm = em * sizeof(TG), bgp = ep * sizeof(TG);
+    const unsigned bc0 = e0 * 4u, bcm = em * 4u, bcp = ep * 4u;
     const bool rm_ok = x_int && (yg - 1 >= 1);
     const bool r0_ok = x_int && (yg >= 1) && (yg <= L.ny - 1);
     const bool rp_ok = x_int && (yg + 1 <= L.ny - 1);
-    constexpr bool JAC = (MODE == M_JAC2 || MODE == M_JAC2_ADD);
 
-    // per plane: values (operand, or omega D^-1 g for the fused two-sweep Jacobi)
-    auto load_plane = [&](int zp, Rows<R> &v, float &cc, Z<R> &gc) {
-        v.a = v.b = v.c = Z<R>{0, 0};
-        cc = 1.0f;
-        gc = Z<R>{0, 0};
-        if (zp < 1 || zp > L.nz - 1) return;
-        const long long pz = (long long)zp * L.sy + rowoff;
-        if (r0_ok) cc = L.c[pz];
-        if (!JAC) {
-            if (rm_ok) v.a = ld<R>(x, pz - L.sx);
-            if (r0_ok) v.b = ld<R>(x, pz);
-            if (rp_ok) v.c = ld<R>(x, pz + L.sx);
-            if (MODE == M_RESID || MODE == M_JSWEEP) {
-                if (r0_ok) gc = ld<R>(g, pz);
-            }
-        } else {
-            const R *wzp = L.wz + 6 * zp;
-            Z<R> wzc = {wzp[2], wzp[3]};
-            Z<R> wxc = wx[1];
-            if (rm_ok) {
-                Z<R> gv = ld<R>(g, pz - L.sx);
-                Coef<R> cf = coef_at(L, stab, L.c[pz - L.sx]);
-                Z<R> D = diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, zadd(wxc, zadd(wyc_m, wzc)));
-                v.a = zscale(omegaJ, zdiv(gv, D));
-            }
-            if (r0_ok) {
-                gc = ld<R>(g, pz);
-                Coef<R> cf = coef_at(L, stab, cc);
-                Z<R> D = diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, zadd(wxc, zadd(wy[1], wzc)));
-                v.b = zscale(omegaJ, zdiv(gc, D));
-            }
-            if (rp_ok) {
-                Z<R> gv = ld<R>(g, pz + L.sx);
-                Coef<R> cf = coef_at(L, stab, L.c[pz + L.sx]);
-                Z<R> D = diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, zadd(wxc, zadd(wyc_p, wzc)));
-                v.c = zscale(omegaJ, zdiv(gv, D));
-            }
+    Z<R> wx[3] = {{0, 0}, {0, 0}, {0, 0}}, wy[3] = {{0, 0}, {0, 0}, {0, 0}};
+    Z<R> wyc_m = {0, 0}, wyc_p = {0, 0};
+    {
+        const R *w = L.wx + 6 * xc;
+        wx[0] = {w[0], w[1]}; wx[1] = {w[2], w[3]}; wx[2] = {w[4], w[5]};
+        const R *v = L.wy + 6 * yg;
+        wy[0] = {v[0], v[1]}; wy[1] = {v[2], v[3]}; wy[2] = {v[4], v[5]};
+        if (JAC) {
+            wyc_m = {L.wy[6 * ym + 2], L.wy[6 * ym + 3]};
+            wyc_p = {L.wy[6 * yp + 2], L.wy[6 * yp + 3]};
         }
+    }
+    const Z<R> zero = {0, 0};
+
+    // Raw loads of one plane (issued one plane ahead of their use).
+    struct Raw {
+        TX va, vb, vc;     // operand rows (or the right-hand side rows in the Jacobi modes)
+        TG gb;             // right-hand side at the centre
+        float ca, cb, cc;  // velocity rows (ca, cc only in the Jacobi modes)
+        int zp;
+    };
+    auto issue = [&](int zp, Raw &r) {
+        const int zc = min(max(zp, 0), L.nz);
+        r.zp = zp;
+        const float *cp = plane_ptr(L.c, L.sy, zc);
+        r.cb = at_byte(cp, bc0);
+        if (!JAC) {
+            const TX *xp = plane_ptr(x, L.sy, zc);
+            r.va = at_byte(xp, bxm);
+            r.vb = at_byte(xp, bx0);
+            r.vc = at_byte(xp, bxp);
+            if (NEED_G) r.gb = at_byte(plane_ptr(g, L.sy, zc), bg0);
+        } else {
+            const TG *gp = plane_ptr(g, L.sy, zc);
+            r.va = at_byte(gp, bgm);
+            r.vb = at_byte(gp, bg0);
+            r.vc = at_byte(gp, bgp);
+            r.ca = at_byte(cp, bcm);
+            r.cc = at_byte(cp, bcp);
+        }
+    };
+    // mask boundary / out-of-box values and form the plane partials
+    auto finish = [&](const Raw &r, Plane<R> &P) {
+        const int zp = r.zp;
+        const bool zok = (zp >= 1 && zp <= L.nz - 1);
+        Z<R> a = {(R)r.va.re, (R)r.va.im}, b = {(R)r.vb.re, (R)r.vb.im}, c = {(R)r.vc.re, (R)r.vc.im};
+        Z<R> gc = zero;
+        if (!JAC) {
+            if (NEED_G) gc = {(R)r.gb.re, (R)r.gb.im};
+        } else {
+            // fused two-sweep Jacobi: the operand is y1 = omega D^-1 g at every loaded node
+            const int zc = min(max(zp, 0), L.nz);
+            const R *wzp = L.wz + 6 * zc;
+            const Z<R> wxz = zadd(wx[1], Z<R>{wzp[2], wzp[3]});
+            const Coef<R> fa = coef_at(L, stab, r.ca), fb = coef_at(L, stab, r.cb), fc = coef_at(L, stab, r.cc);
+            const Z<R> Da = diag_of<R, SHIFT>(L, fa.a1, fa.a4, fa.k2, zadd(wxz, wyc_m));
+            const Z<R> Db = diag_of<R, SHIFT>(L, fb.a1, fb.a4, fb.k2, zadd(wxz, wy[1]));
+            const Z<R> Dc = diag_of<R, SHIFT>(L, fc.a1, fc.a4, fc.k2, zadd(wxz, wyc_p));
+            gc = b;
+            a = zscale(omegaJ, zdiv(a, Da));
+            b = zscale(omegaJ, zdiv(b, Db));
+            c = zscale(omegaJ, zdiv(c, Dc));
+        }
+        if (!(zok && rm_ok)) a = zero;
+        if (!(zok && r0_ok)) b = zero;
+        if (!(zok && rp_ok)) c = zero;
+        P.cc = r.cb;
+        P.gc = gc;
+        plane_partials<R, XI, YI>(a, b, c, wx, wy, P);
     };
 
     const bool yint = (yg >= 1 && yg <= L.ny - 1);
-    Plane<R> Pm, Po, Pp;
-    float cm = 1.f, co = 1.f, cp = 1.f;
-    Z<R> gm = {0, 0}, go = {0, 0}, gp = {0, 0};
-    Rows<R> cur, nxt;
-    float cnx;
-    Z<R> gnx;
-    load_plane(z0 - 1, cur, cm, gm);
-    Pm = plane_partials<R, XYI>(cur, wx, wy);
-    load_plane(z0, cur, co, go);
-    load_plane(z0 + 1, nxt, cnx, gnx);
-    Po = plane_partials<R, XYI>(cur, wx, wy);
-    for (int z = z0; z < z1; ++z) {
-        cur = nxt;
-        cp = cnx;
-        gp = gnx;
-        if (z + 2 <= z1) load_plane(z + 2, nxt, cnx, gnx);   // prefetch the plane after next
-        Pp = plane_partials<R, XYI>(cur, wx, wy);
-        // ---- output plane z ----
-        if (out_lane) {
-            const long long oi = (long long)z * L.sy + rowoff;
-            const bool interior = x_int && yint && z >= 1 && z <= L.nz - 1;
-            Z<R> res = {0, 0};
-            if (interior) {
-                Coef<R> cf = coef_at(L, stab, co);
-                const bool zint = (z >= L.loz && z <= L.hiz);
-                Z<R> wz[3];
-                const R *wzp = L.wz + 6 * z;
-                wz[0] = {wzp[0], wzp[1]}; wz[1] = {wzp[2], wzp[3]}; wz[2] = {wzp[4], wzp[5]};
-                Z<R> Hv = row_value<R, XYI, SHIFT>(L, cf, Pm, Po, Pp, zint, wz);
-                if (MODE == M_APPLY) {
-                    res = Hv;
-                } else if (MODE == M_RESID) {
-                    res = zsub(go, Hv);
-                } else {
-                    Z<R> D = diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, zadd(wx[1], zadd(wy[1], wz[1])));
-                    Z<R> upd = zscale(omegaJ, zdiv(zsub(go, Hv), D));
-                    res = zadd(Po.p0, upd);   // p0 holds the operand (JSWEEP) or omega D^-1 g (JAC2)
-                }
+    // output plane z from planes m, o, p
+    auto emit = [&](int z, const Plane<R> &m, const Plane<R> &o, const Plane<R> &p) {
+        Z<R> res = zero;
+        const bool interior = x_int && yint && z >= 1 && z <= L.nz - 1;
+        if (interior) {
+            const Coef<R> cf = coef_at(L, stab, o.cc);
+            const bool zint = (z >= L.loz && z <= L.hiz);
+            const R *wzp = L.wz + 6 * z;
+            const Z<R> wz[3] = {{wzp[0], wzp[1]}, {wzp[2], wzp[3]}, {wzp[4], wzp[5]}};
+            const Z<R> Hv = row_value<R, XI && YI, SHIFT>(L, cf, m, o, p, zint, wz);
+            if (MODE == M_APPLY) {
+                res = Hv;
+            } else if (MODE == M_RESID) {
+                res = zsub(o.gc, Hv);
+            } else {
+                const Z<R> D = diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, zadd(wx[1], zadd(wy[1], wz[1])));
+                res = zadd(o.p0, zscale(omegaJ, zdiv(zsub(o.gc, Hv), D)));   // p0: operand / y1
             }
-            if (MODE == M_JAC2_ADD) res = zadd(res, ld<R>(base, oi));
-            TY o;
-            o.re = res.r;
-            o.im = res.i;
-            y[oi] = o;
+        }
+        TY *yp_ = const_cast<TY *>(plane_ptr(y, L.sy, z));
+        if (MODE == M_JAC2_ADD) {
+            const TY bv = at_byte(plane_ptr(base, L.sy, z), e0 * (unsigned)sizeof(TY));
+            res.r += (R)bv.re;
+            res.i += (R)bv.im;
+        }
+        if (out_lane) {
+            TY ov;
+            ov.re = res.r;
+            ov.im = res.i;
+            *reinterpret_cast<TY *>(reinterpret_cast<char *>(yp_) + e0 * (unsigned)sizeof(TY)) = ov;
             if (NORM) nrm += (double)res.r * (double)res.r + (double)res.i * (double)res.i;
         }
-        Pm = Po;
-        Po = Pp;
-        co = cp;
-        go = gp;
-        (void)cm;
-        (void)gm;
+    };
+
+    // Two planes of loads stay in flight: a step issues plane z+3, forms the
+    // output of plane z, then turns the already-arrived plane z+2 into partial
+    // sums.  Plane slots rotate with period 3 and load buffers with period 2.
+    Plane<R> P0, P1, P2;
+    Raw ra, rb;
+    issue(z0 - 1, ra);
+    issue(z0, rb);
+    finish(ra, P0);
+    issue(z0 + 1, ra);
+    finish(rb, P1);
+    issue(z0 + 2, rb);
+    finish(ra, P2);
+    auto step = [&](int z, const Plane<R> &m, const Plane<R> &o, const Plane<R> &p, Plane<R> &slot,
+                    const Raw &arrived, Raw &next) -> bool {
+        if (z + 3 <= z1) issue(z + 3, next);
+        emit(z, m, o, p);
+        if (z + 1 >= z1) return false;
+        finish(arrived, slot);   // slot (held plane z-1) now holds plane z+2
+        return true;
+    };
+    for (int z = z0;; z += 6) {
+        if (!step(z, P0, P1, P2, P0, rb, ra)) break;
+        if (!step(z + 1, P1, P2, P0, P1, ra, rb)) break;
+        if (!step(z + 2, P2, P0, P1, P2, rb, ra)) break;
+        if (!step(z + 3, P0, P1, P2, P0, ra, rb)) break;
+        if (!step(z + 4, P1, P2, P0, P1, rb, ra)) break;
+        if (!step(z + 5, P2, P0, P1, P2, ra, rb)) break;
     }
 }
 
@@ -434,15 +497,22 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
     double nrm = 0.0;
     if (yg <= L.ny) {
         const bool out_lane = (lane >= 1 && lane <= kTileX && xg <= L.nx);
-        // whole wave free of x/y stretching?
+        // stretching of this wave: identity along x for all its output columns, along y for its row
         const int xa = max(1, xt * kTileX), xb = min(xt * kTileX + kTileX - 1, L.nx - 1);
-        const bool xyi = (yg >= L.loy && yg <= L.hiy) && (xa > xb || (xa >= L.lox && xb <= L.hix));
-        if (xyi)
-            march<R, TX, TG, TY, MODE, SHIFT, NORM, true>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1, out_lane,
-                                                          nrm);
+        const bool xi = (xa > xb) || (xa >= L.lox && xb <= L.hix);
+        const bool yi = (yg >= L.loy && yg <= L.hiy) || yg < 1 || yg > L.ny - 1;
+        if (xi && yi)
+            march<R, TX, TG, TY, MODE, SHIFT, NORM, true, true>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1,
+                                                                out_lane, nrm);
+        else if (xi)
+            march<R, TX, TG, TY, MODE, SHIFT, NORM, true, false>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1,
+                                                                 out_lane, nrm);
+        else if (yi)
+            march<R, TX, TG, TY, MODE, SHIFT, NORM, false, true>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1,
+                                                                 out_lane, nrm);
         else
-            march<R, TX, TG, TY, MODE, SHIFT, NORM, false>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1, out_lane,
-                                                           nrm);
+            march<R, TX, TG, TY, MODE, SHIFT, NORM, false, false>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1,
+                                                                  out_lane, nrm);
     }
     if (NORM) {
         block_reduce_store(nrm, rb.partials + blockIdx.x);

@@ -38,7 +38,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block-reduce NS complex sums, store them as this block's partials, then
-// return true in the last block (whose threads see every block's partials).
+// return true in the last block to arrive (which may read every block's partials).
 template <int NS>
 __device__ bool reduce_partials(D2 (&acc)[NS], const RedBuf &rb) {
     __shared__ double red[4][2 * kSlots];
@@ -55,40 +55,42 @@ __device__ bool reduce_partials(D2 (&acc)[NS], const RedBuf &rb) {
     __syncthreads();
     if (threadIdx.x < 2 * NS) {
         double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        rb.partials[(size_t)blockIdx.x * 2 * kSlots + threadIdx.x] = v;
+        partial_store(rb.partials + (size_t)blockIdx.x * 2 * kSlots + threadIdx.x, v);
+        stores_done();
     }
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(rb.counter, 1u) == gridDim.x - 1);
+    if (threadIdx.x == 0) last = take_ticket(rb.counter, gridDim.x);
     __syncthreads();
-    if (last) __threadfence();
     return last;
 }
 
-// In the last block: total of slot s over all blocks (fixed order), into out[s].
+// In the last block: total of every slot over all blocks, in a fixed order.
+// Thread t owns slot q = t % (2 NS) and the blocks b = t / (2 NS) + k * G
+// (G = 256 / (2 NS) groups); each thread issues its independent loads back
+// to back, then the G group sums are added in order.
 template <int NS>
 __device__ void sum_partials(const RedBuf &rb, D2 *out) {
-    __shared__ double tree[256];
+    constexpr int NQ = 2 * NS;
+    constexpr int G = 256 / NQ > 0 ? 256 / NQ : 1;
+    __shared__ double grp[256];
     const int nb = gridDim.x;
-    for (int q = 0; q < 2 * NS; ++q) {
-        double v = 0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x)
-            v += __hip_atomic_load(rb.partials + (size_t)b * 2 * kSlots + q, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        tree[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
-            if (threadIdx.x < off) tree[threadIdx.x] += tree[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (q & 1)
-                out[q >> 1].i = tree[0];
-            else
-                out[q >> 1].r = tree[0];
-        }
-        __syncthreads();
+    const int t = threadIdx.x;
+    double v = 0.0;
+    if (t < G * NQ) {
+        const int q = t % NQ, g0 = t / NQ;
+        for (int b = g0; b < nb; b += G) v += partial_load(rb.partials + (size_t)b * 2 * kSlots + q);
     }
+    grp[t] = v;
+    __syncthreads();
+    if (t < NQ) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g) s += grp[g * NQ + t];
+        if (t & 1)
+            out[t >> 1].i = s;
+        else
+            out[t >> 1].r = s;
+    }
+    __syncthreads();
 }
 
 __device__ void state_init(KState *st, double beta) {
@@ -192,7 +194,7 @@ __global__ void __launch_bounds__(256) k_dots(Ptrs<T, NV> P, const T *__restrict
         } else if (EPI == EPI_NORM_INIT) {
             state_init(st, sqrt(tot[NS - 1].r));
         }
-        *rb.counter = 0u;
+        reset_ticket(rb.counter);
     }
 }
 
@@ -244,7 +246,7 @@ __global__ void __launch_bounds__(256) k_axpy_dots(Ptrs<T, NV> P, T *__restrict_
         // ||w - V h2||^2 = ||w||^2 - ||h2||^2 for orthonormal V
         const double hk1 = sqrt(fmax(tot[NV].r - c2, 0.0));
         givens_column(st, NV - 1, h, hk1);
-        *rb.counter = 0u;
+        reset_ticket(rb.counter);
     }
 }
 
@@ -430,7 +432,7 @@ __global__ void __launch_bounds__(256) k_gram(Ptrs<T, NP> P, long long n, KState
             st->y[i][1] = ai / Lr[i][i];
         }
         if (!(G[0][0][0] == G[0][0][0]) || !(G[0][0][0] < 1e300)) st->nonfinite = 1;
-        *rb.counter = 0u;
+        reset_ticket(rb.counter);
     }
 }
 
@@ -513,25 +515,24 @@ __global__ void __launch_bounds__(256) k_velocity_check(const float *__restrict_
             red[0][1] = fmax(red[0][1], red[k][1]);
             red[0][2] += red[k][2];
         }
-        rb.partials[3 * blockIdx.x + 0] = red[0][0];
-        rb.partials[3 * blockIdx.x + 1] = red[0][1];
-        rb.partials[3 * blockIdx.x + 2] = red[0][2];
-        __threadfence();
-        last = (atomicAdd(rb.counter, 1u) == gridDim.x - 1);
+        partial_store(rb.partials + 3 * blockIdx.x + 0, red[0][0]);
+        partial_store(rb.partials + 3 * blockIdx.x + 1, red[0][1]);
+        partial_store(rb.partials + 3 * blockIdx.x + 2, red[0][2]);
+        stores_done();
+        last = take_ticket(rb.counter, gridDim.x);
     }
     __syncthreads();
     if (last && threadIdx.x == 0) {
-        __threadfence();
         double a = 1e300, b = -1e300, c = 0;
         for (unsigned k = 0; k < gridDim.x; ++k) {
-            a = fmin(a, __hip_atomic_load(rb.partials + 3 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            b = fmax(b, __hip_atomic_load(rb.partials + 3 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            c += __hip_atomic_load(rb.partials + 3 * k + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a = fmin(a, partial_load(rb.partials + 3 * k));
+            b = fmax(b, partial_load(rb.partials + 3 * k + 1));
+            c += partial_load(rb.partials + 3 * k + 2);
         }
         out[0] = a;
         out[1] = b;
         out[2] = c;
-        *rb.counter = 0u;
+        reset_ticket(rb.counter);
     }
 }
 
