@@ -141,7 +141,8 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     Hp->st_bottom = c.take<KState>(1);
     Hp->st_hook = c.take<KState>(1);
     size_t np = (size_t)kRedBlocks * 2 * 48;
-    for (int l = 0; l < 3; ++l) np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2]));
+    for (int l = 0; l < 3; ++l)
+        np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2], kTzCandidates[0]));
     Hp->rb.partials = c.take<double>(np);
     Hp->rb.counter = c.take<unsigned>(64);
     Hp->dscratch = c.take<double>(256);
@@ -232,6 +233,7 @@ void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, con
     L.omega_ell = (R)(H->omega * g.ell);
     L.inv_ell2 = (R)(1.0 / (g.ell * g.ell));
     L.sigma = (R)H->opt.sigma;
+    L.tz = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -479,6 +481,51 @@ helm_status dispatch(helm_hierarchy *H, F &&f) {
 
 bool level_ok(int l) { return l >= 0 && l <= 2; }
 
+// Pick, per level, the number of z planes each stencil wavefront marches
+// through: time the level-operator apply (HIP events on the caller's stream)
+// for every candidate and keep the fastest.  Long marches amortise the plane
+// pipeline; short ones give small grids enough workgroups.
+template <typename T>
+hipError_t tune_level_tiles(helm_hierarchy *H, int l) {
+    Eng<T> E(H);
+    T *x = static_cast<T *>(H->tmp[l]);
+    T *y = static_cast<T *>(l == 0 ? H->Vs[0] : (l == 1 ? H->vy : H->e4));
+    HIP_CHK(launch_fill_zero<T>(x, E.nn(l), H->s));
+    hipEvent_t a, b;
+    HIP_CHK(hipEventCreate(&a));
+    HIP_CHK(hipEventCreate(&b));
+    float best = 1e30f;
+    int best_tz = 0;
+    hipError_t err = hipSuccess;
+    for (int tz : kTzCandidates) {
+        if (tz > H->geom[l].n[2] + 1 && tz != kTzCandidates[0]) break;
+        H->Lf[l].tz = H->Ld[l].tz = tz;
+        if ((err = E.stencil(l, M_APPLY, false, 0.0, x, nullptr, nullptr, y)) != hipSuccess) break;
+        if ((err = hipEventRecord(a, H->s)) != hipSuccess) break;
+        for (int r = 0; r < 3 && err == hipSuccess; ++r) err = E.stencil(l, M_APPLY, false, 0.0, x, nullptr, nullptr, y);
+        if (err != hipSuccess || (err = hipEventRecord(b, H->s)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(b)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((err = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+        if (ms < best) {
+            best = ms;
+            best_tz = tz;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    H->Lf[l].tz = H->Ld[l].tz = best_tz;
+    return err;
+}
+
+hipError_t tune_tiles(helm_hierarchy *H) {
+    for (int l = 0; l < 3; ++l) {
+        hipError_t e = (H->prec == HELM_FP64) ? tune_level_tiles<c64>(H, l) : tune_level_tiles<c32>(H, l);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -607,6 +654,7 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
         fill_level_args<float>(H, l, H->Lf[l], H->wf[l][0], H->wf[l][1], H->wf[l][2], H->atab_f, H->btab_f);
         fill_level_args<double>(H, l, H->Ld[l], H->wd[l][0], H->wd[l][1], H->wd[l][2], H->atab_d, H->btab_d);
     }
+    if ((e = tune_tiles(H)) != hipSuccess) return bail(HELM_EHIP, std::string("tile tuning: ") + hipGetErrorString(e));
     *out = H;
     return HELM_OK;
 }

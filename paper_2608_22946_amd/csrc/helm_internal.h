@@ -53,6 +53,7 @@ struct LevelArgs {
     R omega_ell;         // omega * ell
     R inv_ell2;
     R sigma;
+    int tz;              // z planes per wavefront in the stencil kernels (0: default rule)
 };
 
 // ---------------------------------------------------------------------------
@@ -155,7 +156,8 @@ hipError_t launch_add(const T *x, T *y, long long n, hipStream_t s);   // y += x
 template <typename R, typename T>
 hipError_t launch_jac1(const LevelArgs<R> &L, int shifted, double omegaJ, const T *g, T *y, hipStream_t s);
 
-int stencil_blocks(int nx, int ny, int nz);   // grid size of launch_stencil on a level
+int stencil_blocks(int nx, int ny, int nz, int tz);   // grid size of launch_stencil on a level (tz 0: default)
+constexpr int kTzCandidates[] = {2, 4, 8, 16, 32, 64};
 
 template <typename TI, typename TO>
 hipError_t launch_convert(const TI *x, TO *y, long long n, hipStream_t s);

@@ -236,15 +236,22 @@ __device__ __forceinline__ Z<R> row_value(const LevelArgs<R> &L, const Coef<R> &
         St = zadd(St, zscale(t1, zadd(ebo, zadd(eam, eap))));
         St = zadd(St, zscale(t2, zadd(ebm, ebp)));
         // z-direction second difference with transverse weights
-        Z<R> z0 = zmul(wz[1], o.p0);
-        z0 = zfma(wz[0], m.p0, z0);
-        z0 = zfma(wz[2], p.p0, z0);
-        Z<R> z1 = zmul(wz[1], o.p1);
-        z1 = zfma(wz[0], m.p1, z1);
-        z1 = zfma(wz[2], p.p1, z1);
-        Z<R> z2 = zmul(wz[1], o.p2);
-        z2 = zfma(wz[0], m.p2, z2);
-        z2 = zfma(wz[2], p.p2, z2);
+        Z<R> z0, z1, z2;
+        if (zint) {   // unit z stretching: -1, 2, -1
+            z0 = zsub(zscale((R)2, o.p0), zadd(m.p0, p.p0));
+            z1 = zsub(zscale((R)2, o.p1), zadd(m.p1, p.p1));
+            z2 = zsub(zscale((R)2, o.p2), zadd(m.p2, p.p2));
+        } else {
+            z0 = zmul(wz[1], o.p0);
+            z0 = zfma(wz[0], m.p0, z0);
+            z0 = zfma(wz[2], p.p0, z0);
+            z1 = zmul(wz[1], o.p1);
+            z1 = zfma(wz[0], m.p1, z1);
+            z1 = zfma(wz[2], p.p1, z1);
+            z2 = zmul(wz[1], o.p2);
+            z2 = zfma(wz[0], m.p2, z2);
+            z2 = zfma(wz[2], p.p2, z2);
+        }
         St = zadd(St, zscale(t0, z0));
         St = zadd(St, zscale(t1, z1));
         St = zadd(St, zscale(t2, z2));
@@ -283,6 +290,7 @@ __device__ void norm_epilogue(const RedBuf &rb, int nblocks, KState *st) {
     __syncthreads();
     if (!last) return;
     double s = 0;
+#pragma unroll 8
     for (int b = tid; b < nblocks; b += 256) s += partial_load(rb.partials + b);
     red[tid] = s;
     __syncthreads();
@@ -471,6 +479,20 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
     }
 }
 
+// Edge strips of kEdge output columns each (x = 0..29 and nx-29..nx) share one
+// wavefront when both x-PML strips fit inside them.
+constexpr int kEdge = 30;
+
+template <typename R>
+__host__ __device__ __forceinline__ bool split_edges(const LevelArgs<R> &L) {
+    return L.nx >= 2 * kEdge && L.lox >= 1 && L.lox <= kEdge && L.hix >= L.nx - kEdge;
+}
+
+template <typename R>
+int x_tiles(const LevelArgs<R> &L) {
+    return split_edges(L) ? 1 + ceil_div(L.nx - 2 * kEdge + 1, kTileX) : ceil_div(L.nx + 1, kTileX);
+}
+
 template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM>
 __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
                                                  const TY *__restrict__ base, TY *__restrict__ y, R omegaJ, int ntx,
@@ -490,16 +512,32 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
     const int yt = t % nty;
     const int zc = t / nty;
     const int lane = threadIdx.x;
-    const int xg = xt * kTileX - 1 + lane;
     const int yg = yt * kWavesY + threadIdx.y;
     const int z0 = zc * tz;
     const int z1 = min(z0 + tz, L.nz + 1);
+    // x tiling: with split edges, tile 0 holds both x edge strips (lanes 0..31:
+    // x = -1..30, lanes 32..63: x = nx-30..nx+1; lanes 31 and 32 are halo only),
+    // so every other tile is free of x stretching; otherwise 62-column tiles.
+    int xg;
+    bool out_lane, xi;
+    if (split_edges(L)) {
+        if (xt == 0) {
+            xg = lane < 32 ? lane - 1 : L.nx - kEdge + (lane - 32);
+            out_lane = (lane >= 1 && lane <= kEdge) || (lane >= 33 && lane <= 62);
+            xi = (L.lox <= 1 && L.hix >= L.nx - 1);
+        } else {
+            xg = kEdge - 1 + (xt - 1) * kTileX + lane;
+            out_lane = (lane >= 1 && lane <= kTileX && xg <= L.nx - kEdge);
+            xi = true;
+        }
+    } else {
+        xg = xt * kTileX - 1 + lane;
+        out_lane = (lane >= 1 && lane <= kTileX && xg <= L.nx);
+        const int xa = max(1, xt * kTileX), xb = min(xt * kTileX + kTileX - 1, L.nx - 1);
+        xi = (xa > xb) || (xa >= L.lox && xb <= L.hix);
+    }
     double nrm = 0.0;
     if (yg <= L.ny) {
-        const bool out_lane = (lane >= 1 && lane <= kTileX && xg <= L.nx);
-        // stretching of this wave: identity along x for all its output columns, along y for its row
-        const int xa = max(1, xt * kTileX), xb = min(xt * kTileX + kTileX - 1, L.nx - 1);
-        const bool xi = (xa > xb) || (xa >= L.lox && xb <= L.hix);
         const bool yi = (yg >= L.loy && yg <= L.hiy) || yg < 1 || yg > L.ny - 1;
         if (xi && yi)
             march<R, TX, TG, TY, MODE, SHIFT, NORM, true, true>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1,
@@ -624,9 +662,9 @@ int pick_tz(int ntx, int nty, int nz1) {
 
 template <typename R, typename TX, typename TG, typename TY>
 hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, hipStream_t s) {
-    const int ntx = ceil_div(L.nx + 1, kTileX);
+    const int ntx = x_tiles(L);
     const int nty = ceil_div(L.ny + 1, kWavesY);
-    const int tz = pick_tz(ntx, nty, L.nz + 1);
+    const int tz = L.tz > 0 ? L.tz : pick_tz(ntx, nty, L.nz + 1);
     const int nzc = ceil_div(L.nz + 1, tz);
     const int blocks = ntx * nty * nzc;
     const dim3 blk(64, kWavesY);
@@ -670,10 +708,10 @@ hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const Red
     return hipGetLastError();
 }
 
-int stencil_blocks(int nx, int ny, int nz) {
-    const int ntx = ceil_div(nx + 1, kTileX);
+int stencil_blocks(int nx, int ny, int nz, int tz) {
+    const int ntx = 1 + ceil_div(nx + 1, kTileX);   // upper bound for both x tilings
     const int nty = ceil_div(ny + 1, kWavesY);
-    const int tz = pick_tz(ntx, nty, nz + 1);
+    if (tz <= 0) tz = pick_tz(ntx, nty, nz + 1);
     return ntx * nty * ceil_div(nz + 1, tz);
 }
 

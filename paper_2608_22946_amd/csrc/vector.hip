@@ -39,9 +39,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Block-reduce NS complex sums, store them as this block's partials, then
 // return true in the last block to arrive (which may read every block's partials).
+constexpr int kRedThreads = 1024;      // threads per reduction block (16 wavefronts)
+constexpr int kRedWaves = kRedThreads / 64;
+
 template <int NS>
 __device__ bool reduce_partials(D2 (&acc)[NS], const RedBuf &rb) {
-    __shared__ double red[4][2 * kSlots];
+    __shared__ double red[kRedWaves][2 * kSlots];
     __shared__ bool last;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -54,7 +57,8 @@ __device__ bool reduce_partials(D2 (&acc)[NS], const RedBuf &rb) {
     }
     __syncthreads();
     if (threadIdx.x < 2 * NS) {
-        double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        double v = 0.0;
+        for (int k = 0; k < kRedWaves; ++k) v += red[k][threadIdx.x];
         partial_store(rb.partials + (size_t)blockIdx.x * 2 * kSlots + threadIdx.x, v);
         stores_done();
     }
@@ -66,18 +70,19 @@ __device__ bool reduce_partials(D2 (&acc)[NS], const RedBuf &rb) {
 
 // In the last block: total of every slot over all blocks, in a fixed order.
 // Thread t owns slot q = t % (2 NS) and the blocks b = t / (2 NS) + k * G
-// (G = 256 / (2 NS) groups); each thread issues its independent loads back
-// to back, then the G group sums are added in order.
+// (G = blockDim / (2 NS) groups); its loads are independent and unrolled, then
+// the G group sums are added in order.
 template <int NS>
 __device__ void sum_partials(const RedBuf &rb, D2 *out) {
     constexpr int NQ = 2 * NS;
-    constexpr int G = 256 / NQ > 0 ? 256 / NQ : 1;
-    __shared__ double grp[256];
+    constexpr int G = kRedThreads / NQ > 0 ? kRedThreads / NQ : 1;
+    __shared__ double grp[kRedThreads];
     const int nb = gridDim.x;
     const int t = threadIdx.x;
     double v = 0.0;
     if (t < G * NQ) {
         const int q = t % NQ, g0 = t / NQ;
+#pragma unroll 8
         for (int b = g0; b < nb; b += G) v += partial_load(rb.partials + (size_t)b * 2 * kSlots + q);
     }
     grp[t] = v;
@@ -164,13 +169,14 @@ struct Ptrs {
 
 // sums conj(V_j) w (j < NV) and optionally ||w||^2
 template <typename T, int NV, bool NORM, int EPI>
-__global__ void __launch_bounds__(256) k_dots(Ptrs<T, NV> P, const T *__restrict__ w, long long n, KState *st,
+__global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restrict__ w, long long n, KState *st,
                                              double *out, RedBuf rb) {
     constexpr int NS0 = NV + (NORM ? 1 : 0);
     constexpr int NS = NS0 > 0 ? NS0 : 1;
     D2 acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = {0, 0};
+#pragma unroll 2
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const T wi = w[i];
 #pragma unroll
@@ -200,7 +206,7 @@ __global__ void __launch_bounds__(256) k_dots(Ptrs<T, NV> P, const T *__restrict
 
 // w <- w - sum_j h1_j V_j; then conj(V_j) w and ||w||^2; Givens update of column NV-1
 template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_axpy_dots(Ptrs<T, NV> P, T *__restrict__ w, long long n, KState *st,
+__global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict__ w, long long n, KState *st,
                                                   RedBuf rb) {
     __shared__ double hs[NV][2];
     if (threadIdx.x < NV) {
@@ -217,6 +223,7 @@ __global__ void __launch_bounds__(256) k_axpy_dots(Ptrs<T, NV> P, T *__restrict_
     D2 acc[NV + 1];
 #pragma unroll
     for (int s = 0; s <= NV; ++s) acc[s] = {0, 0};
+#pragma unroll 2
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         T v[NV];
         T wi = w[i];
@@ -356,11 +363,12 @@ __global__ void __launch_bounds__(256) k_combine(TX *__restrict__ x, Ptrs<TZ, NV
 // the least-squares coefficients y of min ||P_0 - [P_1..P_{NP-1}] y|| from the
 // normal equations by Cholesky (truncated at a vanishing pivot).
 template <typename T, int NP>
-__global__ void __launch_bounds__(256) k_gram(Ptrs<T, NP> P, long long n, KState *st, RedBuf rb) {
+__global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KState *st, RedBuf rb) {
     constexpr int NS = NP * (NP + 1) / 2;
     D2 acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = {0, 0};
+#pragma unroll 2
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         T v[NP];
 #pragma unroll
@@ -536,10 +544,11 @@ __global__ void __launch_bounds__(256) k_velocity_check(const float *__restrict_
     }
 }
 
+// 256 blocks of 1024 threads (one per CU, 16 wavefronts), fewer only for tiny vectors
 int red_blocks(long long n) {
-    long long b = (n + 1023) / 1024;
+    long long b = (n + 2 * kRedThreads - 1) / (2 * kRedThreads);
     if (b < 1) b = 1;
-    if (b > kRedBlocks) b = kRedBlocks;
+    if (b > 256) b = 256;
     return (int)b;
 }
 
@@ -568,19 +577,19 @@ hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long lo
     case NV:                                                                                                        \
         if (norm) {                                                                                                 \
             if (epi == EPI_STORE)                                                                                   \
-                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_STORE>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, n, \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_STORE>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, \
                                    st, out, rb);                                                                    \
             else if (epi == EPI_NORM_INIT)                                                                          \
-                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_NORM_INIT>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_NORM_INIT>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), \
                                    w, n, st, out, rb);                                                              \
             else                                                                                                    \
                 return hipErrorInvalidValue;                                                                        \
         } else {                                                                                                    \
             if (epi == EPI_STORE)                                                                                   \
-                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_STORE>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, \
+                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_STORE>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, \
                                    n, st, out, rb);                                                                 \
             else if (epi == EPI_ARNOLDI1)                                                                           \
-                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_ARNOLDI1>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), \
+                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_ARNOLDI1>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), \
                                    w, n, st, out, rb);                                                              \
             else                                                                                                    \
                 return hipErrorInvalidValue;                                                                        \
@@ -601,7 +610,7 @@ hipError_t launch_axpy_dots(const T *const *V, int nv, T *w, long long n, KState
                             hipStream_t s) {
     const int nb = red_blocks(n);
 #define HELM_AD(NV) \
-    case NV: hipLaunchKernelGGL((k_axpy_dots<T, NV>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, n, st, rb); break;
+    case NV: hipLaunchKernelGGL((k_axpy_dots<T, NV>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, st, rb); break;
     switch (nv) {
         HELM_AD(1) HELM_AD(2) HELM_AD(3) HELM_AD(4) HELM_AD(5) HELM_AD(6) HELM_AD(7) HELM_AD(8) HELM_AD(9)
         HELM_AD(10) HELM_AD(11) HELM_AD(12)
@@ -656,7 +665,7 @@ template <typename T>
 hipError_t launch_gram(const T *const *P, int np, long long n, KState *st, const RedBuf &rb, hipStream_t s) {
     const int nb = red_blocks(n);
 #define HELM_GR(NP) \
-    case NP: hipLaunchKernelGGL((k_gram<T, NP>), dim3(nb), dim3(256), 0, s, pack<T, NP>(P), n, st, rb); break;
+    case NP: hipLaunchKernelGGL((k_gram<T, NP>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NP>(P), n, st, rb); break;
     switch (np) {
         HELM_GR(2) HELM_GR(3) HELM_GR(4) HELM_GR(5) HELM_GR(6) HELM_GR(7) HELM_GR(8) HELM_GR(9)
     default:
