@@ -76,7 +76,7 @@ typedef struct {
     helm_precision precision; /* arithmetic and vector type of the hot path */
     double sigma, omega_h, omega_2h, omega_4h, gamma_max;
     int nJ_h, nJ_2h, nJ_4h;   /* Jacobi sweeps per level, 1..8 */
-    int m_h, c_2h, m_2h, m_4h, m_out; /* m_h, m_2h, m_out in 1..16; m_4h in 1..8; c_2h in 1..8 */
+    int m_h, c_2h, m_2h, m_4h, m_out; /* m_h, m_2h, m_out in 1..12; m_4h in 1..8; c_2h in 1..8 */
     int max_outer;            /* preconditioner calls per right-hand side (<= 0: 1000) */
     const double *iofd_table; /* HOST, (K+1)*8*2 doubles: [node k][function f][value, slope],
                                  f = alpha1..alpha5, beta1..beta3, nodes eta_k = 0.4 k / K.
@@ -84,6 +84,12 @@ typedef struct {
                                  copied during helm_setup. */
     int iofd_K;               /* number of table intervals, 1..128 */
     void *stream;             /* hipStream_t */
+    /* Stencil tiling per level (performance only, results do not depend on it
+     * beyond rounding of the fused norms).  helm_setup times the candidates
+     * that are not fixed here on options.stream and keeps the fastest. */
+    int tile_tz;              /* z planes per wavefront: 0 = timed; else 2, 4, 8, 16, 32 or 64 */
+    int tile_split;           /* -1 = timed; 0 = one launch per stencil; 1 = an interior launch plus
+                                 a border launch where the PML layout allows it */
 } helm_options;
 
 /* Fill *opt with the defaults above (table NULL, stream NULL, FP32). */

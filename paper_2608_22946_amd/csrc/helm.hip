@@ -234,6 +234,7 @@ void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, con
     L.inv_ell2 = (R)(1.0 / (g.ell * g.ell));
     L.sigma = (R)H->opt.sigma;
     L.tz = 0;
+    L.split = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -455,6 +456,10 @@ helm_status check_options(const helm_options *o, std::string &msg) {
     }
     if (!in(o->m_4h, 1, kM4Max) || !in(o->c_2h, 1, 8)) { msg = "m_4h must be in 1..8 and c_2h in 1..8"; return HELM_EINVAL; }
     if (!in(o->iofd_K, 1, kKMax)) { msg = "iofd_K must be in 1..128"; return HELM_EINVAL; }
+    bool tz_ok = o->tile_tz == 0;
+    for (int tz : kTzCandidates) tz_ok = tz_ok || o->tile_tz == tz;
+    if (!tz_ok) { msg = "tile_tz must be 0, 2, 4, 8, 16, 32 or 64"; return HELM_EINVAL; }
+    if (!in(o->tile_split, -1, 1)) { msg = "tile_split must be -1, 0 or 1"; return HELM_EINVAL; }
     return HELM_OK;
 }
 
@@ -482,9 +487,11 @@ helm_status dispatch(helm_hierarchy *H, F &&f) {
 bool level_ok(int l) { return l >= 0 && l <= 2; }
 
 // Pick, per level, the number of z planes each stencil wavefront marches
-// through: time the level-operator apply (HIP events on the caller's stream)
-// for every candidate and keep the fastest.  Long marches amortise the plane
-// pipeline; short ones give small grids enough workgroups.
+// through and whether the stencils run as one launch or as interior + border
+// launches: time an operator apply plus a fused Jacobi pair (HIP events on the
+// caller's stream, best of two trials) for every candidate and keep the fastest.  Long marches amortise the plane
+// pipeline; short ones give small grids enough workgroups; the split costs a
+// second launch but lets interior tiles run at higher occupancy.
 template <typename T>
 hipError_t tune_level_tiles(helm_hierarchy *H, int l) {
     Eng<T> E(H);
@@ -495,30 +502,53 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l) {
     HIP_CHK(hipEventCreate(&a));
     HIP_CHK(hipEventCreate(&b));
     float best = 1e30f;
-    int best_tz = 0;
+    int best_tz = 0, best_split = 0;
     hipError_t err = hipSuccess;
-    for (int tz : kTzCandidates) {
-        if (tz > H->geom[l].n[2] + 1 && tz != kTzCandidates[0]) break;
+    for (int cand = 0; cand < 2 * (int)(sizeof(kTzCandidates) / sizeof(int)) && err == hipSuccess; ++cand) {
+        const int tz = kTzCandidates[cand / 2], split = cand % 2;
+        if (tz > H->geom[l].n[2] + 1 && tz != kTzCandidates[0] && H->opt.tile_tz == 0) break;
+        if ((H->opt.tile_tz != 0 && tz != H->opt.tile_tz) || (H->opt.tile_split >= 0 && split != H->opt.tile_split))
+            continue;
         H->Lf[l].tz = H->Ld[l].tz = tz;
-        if ((err = E.stencil(l, M_APPLY, false, 0.0, x, nullptr, nullptr, y)) != hipSuccess) break;
-        if ((err = hipEventRecord(a, H->s)) != hipSuccess) break;
-        for (int r = 0; r < 3 && err == hipSuccess; ++r) err = E.stencil(l, M_APPLY, false, 0.0, x, nullptr, nullptr, y);
-        if (err != hipSuccess || (err = hipEventRecord(b, H->s)) != hipSuccess) break;
-        if ((err = hipEventSynchronize(b)) != hipSuccess) break;
-        float ms = 0.f;
-        if ((err = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+        H->Lf[l].split = H->Ld[l].split = split;
+        // one operator apply plus one fused two-sweep Jacobi: the two stencil kinds the cycle spends most time in
+        auto pair = [&]() -> hipError_t {
+            hipError_t e = E.stencil(l, M_APPLY, l > 0, 0.0, x, nullptr, nullptr, y);
+            return e != hipSuccess ? e : E.stencil(l, M_JAC2, l > 0, H->opt.omega_h, nullptr, x, nullptr, y);
+        };
+        if ((err = pair()) != hipSuccess) break;
+        float ms = 1e30f;
+        for (int trial = 0; trial < 2 && err == hipSuccess; ++trial) {
+            if ((err = hipEventRecord(a, H->s)) != hipSuccess) break;
+            for (int r = 0; r < 3 && err == hipSuccess; ++r) err = pair();
+            if (err != hipSuccess || (err = hipEventRecord(b, H->s)) != hipSuccess) break;
+            if ((err = hipEventSynchronize(b)) != hipSuccess) break;
+            float t = 0.f;
+            if ((err = hipEventElapsedTime(&t, a, b)) != hipSuccess) break;
+            ms = std::min(ms, t);
+        }
+        if (err != hipSuccess) break;
         if (ms < best) {
             best = ms;
             best_tz = tz;
+            best_split = split;
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     H->Lf[l].tz = H->Ld[l].tz = best_tz;
+    H->Lf[l].split = H->Ld[l].split = best_split;
     return err;
 }
 
 hipError_t tune_tiles(helm_hierarchy *H) {
+    if (H->opt.tile_tz != 0 && H->opt.tile_split >= 0) {
+        for (int l = 0; l < 3; ++l) {
+            H->Lf[l].tz = H->Ld[l].tz = H->opt.tile_tz;
+            H->Lf[l].split = H->Ld[l].split = H->opt.tile_split;
+        }
+        return hipSuccess;
+    }
     for (int l = 0; l < 3; ++l) {
         hipError_t e = (H->prec == HELM_FP64) ? tune_level_tiles<c64>(H, l) : tune_level_tiles<c32>(H, l);
         if (e != hipSuccess) return e;
@@ -553,6 +583,8 @@ helm_status helm_default_options(helm_options *o) {
     o->iofd_table = nullptr;
     o->iofd_K = 0;
     o->stream = nullptr;
+    o->tile_tz = 0;
+    o->tile_split = -1;
     return HELM_OK;
 }
 

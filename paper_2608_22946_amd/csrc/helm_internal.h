@@ -54,6 +54,7 @@ struct LevelArgs {
     R inv_ell2;
     R sigma;
     int tz;              // z planes per wavefront in the stencil kernels (0: default rule)
+    int split;           // 1: stencils run as an interior launch plus a border launch where the tiling allows
 };
 
 // ---------------------------------------------------------------------------

@@ -364,8 +364,13 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
         float ca, cb, cc;  // velocity rows (ca, cc only in the Jacobi modes)
         int zp;
     };
+    // Planes past the tile's last plane z1 are re-read from z1 (a cache hit):
+    // the prefetch is then issued unconditionally, which keeps the count of
+    // outstanding loads the same on every path through the loop, so waiting
+    // for one plane never waits for the planes issued after it.
+    const int zlast = min(z1, L.nz);
     auto issue = [&](int zp, Raw &r) {
-        const int zc = min(max(zp, 0), L.nz);
+        const int zc = min(max(zp, 0), zlast);
         r.zp = zp;
         const float *cp = plane_ptr(L.c, L.sy, zc);
         r.cb = at_byte(cp, bc0);
@@ -463,7 +468,7 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
     finish(ra, P2);
     auto step = [&](int z, const Plane<R> &m, const Plane<R> &o, const Plane<R> &p, Plane<R> &slot,
                     const Raw &arrived, Raw &next) -> bool {
-        if (z + 3 <= z1) issue(z + 3, next);
+        issue(z + 3, next);
         emit(z, m, o, p);
         if (z + 1 >= z1) return false;
         finish(arrived, slot);   // slot (held plane z-1) now holds plane z+2
@@ -493,10 +498,23 @@ int x_tiles(const LevelArgs<R> &L) {
     return split_edges(L) ? 1 + ceil_div(L.nx - 2 * kEdge + 1, kTileX) : ceil_div(L.nx + 1, kTileX);
 }
 
-template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM>
+// Grid of one stencil launch.  PART 0 covers every tile.  With split edges the
+// tiles divide into an interior set (x tiles 1.. and y tiles whose four rows
+// all lie between the y-PML strips, PART 1), which needs no x/y stretching
+// and so compiles to fewer registers, and the remaining border set (PART 2).
+// The two parts are launched back to back; a fused norm spans both through
+// block_offset / total_blocks.
+struct TileMap {
+    int ntx, nty, tz;
+    int yt_lo, nyi;        // interior y tiles: yt_lo .. yt_lo + nyi - 1
+    int block_offset;      // index of this launch's first block among all blocks of the call
+    int total_blocks;      // blocks over all launches of the call
+};
+
+template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM, int PART>
 __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
-                                                 const TY *__restrict__ base, TY *__restrict__ y, R omegaJ, int ntx,
-                                                 int nty, int tz, RedBuf rb, KState *st) {
+                                                 const TY *__restrict__ base, TY *__restrict__ y, R omegaJ, TileMap M,
+                                                 RedBuf rb, KState *st) {
     extern __shared__ unsigned char smem_raw[];
     R *stab = reinterpret_cast<R *>(smem_raw);
     const int tid = threadIdx.x + 64 * threadIdx.y;
@@ -507,14 +525,38 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
     const int nb = gridDim.x, b = blockIdx.x;
     const int per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
     int t = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-    const int xt = t % ntx;
-    t /= ntx;
-    const int yt = t % nty;
-    const int zc = t / nty;
+    const int ntx = M.ntx, nty = M.nty;
+    int xt, yt, zc;
+    if (PART == 0) {
+        xt = t % ntx;
+        t /= ntx;
+        yt = t % nty;
+        zc = t / nty;
+    } else if (PART == 1) {
+        const int nxi = ntx - 1;
+        xt = 1 + t % nxi;
+        t /= nxi;
+        yt = M.yt_lo + t % M.nyi;
+        zc = t / M.nyi;
+    } else {
+        // per z chunk: the edge x tile of every y tile, then the inner x tiles of the y tiles outside the interior
+        const int per_z = nty + (nty - M.nyi) * (ntx - 1);
+        zc = t / per_z;
+        int u = t - zc * per_z;
+        if (u < nty) {
+            xt = 0;
+            yt = u;
+        } else {
+            u -= nty;
+            xt = 1 + u % (ntx - 1);
+            const int yo = u / (ntx - 1);
+            yt = yo < M.yt_lo ? yo : yo + M.nyi;
+        }
+    }
     const int lane = threadIdx.x;
     const int yg = yt * kWavesY + threadIdx.y;
-    const int z0 = zc * tz;
-    const int z1 = min(z0 + tz, L.nz + 1);
+    const int z0 = zc * M.tz;
+    const int z1 = min(z0 + M.tz, L.nz + 1);
     // x tiling: with split edges, tile 0 holds both x edge strips (lanes 0..31:
     // x = -1..30, lanes 32..63: x = nx-30..nx+1; lanes 31 and 32 are halo only),
     // so every other tile is free of x stretching; otherwise 62-column tiles.
@@ -537,7 +579,10 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
         xi = (xa > xb) || (xa >= L.lox && xb <= L.hix);
     }
     double nrm = 0.0;
-    if (yg <= L.ny) {
+    if (PART == 1) {   // interior tiles: unit x/y weights on every row by construction
+        march<R, TX, TG, TY, MODE, SHIFT, NORM, true, true>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1, out_lane,
+                                                            nrm);
+    } else if (yg <= L.ny) {
         const bool yi = (yg >= L.loy && yg <= L.hiy) || yg < 1 || yg > L.ny - 1;
         if (xi && yi)
             march<R, TX, TG, TY, MODE, SHIFT, NORM, true, true>(L, stab, x, g, base, y, omegaJ, xg, yg, z0, z1,
@@ -553,8 +598,8 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
                                                                   out_lane, nrm);
     }
     if (NORM) {
-        block_reduce_store(nrm, rb.partials + blockIdx.x);
-        norm_epilogue(rb, gridDim.x, st);
+        block_reduce_store(nrm, rb.partials + M.block_offset + blockIdx.x);
+        norm_epilogue(rb, M.total_blocks, st);
     }
 }
 
@@ -660,13 +705,9 @@ int pick_tz(int ntx, int nty, int nz1) {
 
 }  // namespace
 
-template <typename R, typename TX, typename TG, typename TY>
-hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, hipStream_t s) {
-    const int ntx = x_tiles(L);
-    const int nty = ceil_div(L.ny + 1, kWavesY);
-    const int tz = L.tz > 0 ? L.tz : pick_tz(ntx, nty, L.nz + 1);
-    const int nzc = ceil_div(L.nz + 1, tz);
-    const int blocks = ntx * nty * nzc;
+template <typename R, typename TX, typename TG, typename TY, int PART>
+hipError_t launch_stencil_part(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, const TileMap &M,
+                               int blocks, hipStream_t s) {
     const dim3 blk(64, kWavesY);
     const size_t shm = sizeof(R) * L.K * 20;
     const TX *x = (const TX *)c.x;
@@ -674,9 +715,9 @@ hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const Red
     const TY *base = (const TY *)c.base;
     TY *y = (TY *)c.y;
     const R om = (R)c.omegaJ;
-#define HELM_LAUNCH(MODE, SH, NRM)                                                                              \
-    hipLaunchKernelGGL((k_stencil<R, TX, TG, TY, MODE, SH, NRM>), dim3(blocks), blk, shm, s, L, x, g, base, y, om, \
-                       ntx, nty, tz, rb, c.st)
+#define HELM_LAUNCH(MODE, SH, NRM)                                                                                 \
+    hipLaunchKernelGGL((k_stencil<R, TX, TG, TY, MODE, SH, NRM, PART>), dim3(blocks), blk, shm, s, L, x, g, base, y, \
+                       om, M, rb, c.st)
     if (c.norm) {
         if (c.mode != M_RESID) return hipErrorInvalidValue;
         if (c.shifted)
@@ -706,6 +747,31 @@ hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const Red
     }
 #undef HELM_LAUNCH
     return hipGetLastError();
+}
+
+template <typename R, typename TX, typename TG, typename TY>
+hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, hipStream_t s) {
+    TileMap M;
+    M.ntx = x_tiles(L);
+    M.nty = ceil_div(L.ny + 1, kWavesY);
+    M.tz = L.tz > 0 ? L.tz : pick_tz(M.ntx, M.nty, L.nz + 1);
+    const int nzc = ceil_div(L.nz + 1, M.tz);
+    const int blocks = M.ntx * M.nty * nzc;
+    // interior y tiles: all kWavesY rows inside [loy, hiy]
+    M.yt_lo = ceil_div(L.loy, kWavesY);
+    M.nyi = std::max(0, (L.hiy + 1) / kWavesY - M.yt_lo);
+    M.block_offset = 0;
+    M.total_blocks = blocks;
+    if (L.split && split_edges(L) && M.ntx > 1 && M.nyi > 0) {
+        const int bi = (M.ntx - 1) * M.nyi * nzc;
+        const int bb = blocks - bi;
+        hipError_t e = launch_stencil_part<R, TX, TG, TY, 2>(L, c, rb, M, bb, s);
+        if (e != hipSuccess) return e;
+        M.block_offset = bb;
+        return launch_stencil_part<R, TX, TG, TY, 1>(L, c, rb, M, bi, s);
+    }
+    M.yt_lo = M.nyi = 0;
+    return launch_stencil_part<R, TX, TG, TY, 0>(L, c, rb, M, blocks, s);
 }
 
 int stencil_blocks(int nx, int ny, int nz, int tz) {

@@ -30,14 +30,14 @@ def to_np(t):
 class Pair:
     """GPU hierarchy and reference checker built from identical inputs."""
 
-    def __init__(self, vel, n_pml, precision, table=None, **params):
+    def __init__(self, vel, n_pml, precision, table=None, tiling=None, **params):
         from oracle.oracle import Hierarchy as OH
         from paper_2608_22946_amd import helm
         table = table or load_iofd_table()
         cmin = float(vel.min())
         self.omega = omega_for_ppw(cmin, H)
         self.g = helm.Hierarchy(torch.from_numpy(vel), H, self.omega, n_pml, precision=precision, table=table,
-                                **params)
+                                **params, **(tiling or {}))
         self.o = OH(vel, H, self.omega, n_pml, table, params=params)
         self.prec = precision
         self.ct = np.complex128 if precision == "fp64" else np.complex64
@@ -193,6 +193,49 @@ def test_no_pml_box():
     assert rel(to_np(p.g.apply(0, 1, p.dev(x))), p.o.apply(0, 1, x)) <= 1e-12
 
 
+# ---- fixed stencil tilings: one launch, or interior + border launches ----
+# GRID allows the split on levels 0 and 1 (x edge strips fit in one wavefront,
+# interior y tiles exist); level 2 always runs as one launch.
+
+TILINGS = [dict(tile_tz=2, tile_split=1), dict(tile_tz=8, tile_split=1), dict(tile_tz=64, tile_split=0)]
+
+
+@pytest.fixture(scope="module", params=[(prec, i) for prec in ("fp64", "fp32") for i in range(len(TILINGS))],
+                ids=lambda p: f"{p[0]}-tz{TILINGS[p[1]]['tile_tz']}-split{TILINGS[p[1]]['tile_split']}")
+def tiled(request):
+    prec, i = request.param
+    vel = grf_velocity(GRID["nx"], GRID["ny"], GRID["nz"], seed=12, corr_len=6.0)
+    return Pair(vel, GRID["n_pml"], prec, tiling=TILINGS[i])
+
+
+def test_tiling_stencils(tiled):
+    p = tiled
+    for level, op in [(0, 0), (0, 1), (1, 1), (2, 1)]:
+        x = p.rand(level, 400 + level + 3 * op)
+        assert rel(to_np(p.g.apply(level, op, p.dev(x))), p.o.apply(level, op, x.astype(complex))) <= \
+            p.tol(1e-12, 1e-6)
+    for level, op in [(0, 0), (1, 1)]:
+        g, x = p.rand(level, 410 + level), p.rand(level, 420 + level)
+        r = to_np(p.g.residual(level, op, p.dev(g), p.dev(x)))
+        assert rel(r, p.o.residual(level, op, g.astype(complex), x.astype(complex))) <= p.tol(1e-12, 1e-6)
+    for level, op, nJ, w in [(0, 0, 2, 0.8), (0, 0, 3, 0.8), (1, 1, 2, 0.8)]:
+        g = p.rand(level, 430 + level + nJ)
+        assert rel(to_np(p.g.jacobi(level, op, p.dev(g), nJ, w)), p.o.jacobi(level, op, g.astype(complex), nJ, w)) \
+            <= p.tol(1e-12, 1e-6)
+
+
+def test_tiling_smooth_and_precond(tiled):
+    """GMRES from a nonzero guess starts with the fused residual norm, which
+    spans both launches of a split stencil."""
+    p = tiled
+    r, x0 = p.rand(0, 440), p.rand(0, 441)
+    err = rel(to_np(p.g.smooth(p.dev(r), p.dev(x0))), p.o.smooth(r.astype(complex), x0.astype(complex)))
+    assert err <= p.tol(1e-10, 1e-4), err
+    r = p.rand(0, 442)
+    err = rel(to_np(p.g.precond(p.dev(r))), p.o.precond(r.astype(complex)))
+    assert err <= p.tol(1e-8, 1e-2), err
+
+
 # ---- whole solve ----
 
 def test_solve_small_config_fp64():
@@ -208,6 +251,26 @@ def test_solve_small_config_fp64():
     err = rel(to_np(u), uo)
     assert err <= 1e-5, (err, its, its_o)
     assert abs(its - its_o) <= 2
+
+
+@pytest.mark.parametrize("tiling", [dict(tile_tz=4, tile_split=1), dict(tile_tz=32, tile_split=0)],
+                         ids=["tz4-split", "tz32-one"])
+def test_solve_fixed_tiling_fp32(tiling):
+    """FP32 solve with the tiling fixed: the outer restart residual norm runs
+    through the split launches; the answer matches the FP64 checker's within
+    the spread of two solves stopped at relative residual 1e-6."""
+    n, npml = 44, 10
+    vel = grf_velocity(n, n, n, seed=21, corr_len=8.0)
+    p = Pair(vel, npml, "fp32", tiling=tiling)
+    N = n + 2 * npml
+    f = point_source((N, N, N), (N // 2 - 3, N // 2 + 2, N // 2), H)
+    u, its, relres, rc = p.g.solve(p.dev(f), 1e-6)
+    assert rc == 0 and relres <= 1e-6
+    uo, its_o, rel_o, st = p.o.solve(f.astype(complex), 1e-6)
+    assert st == 0
+    err = rel(to_np(u), uo)
+    print(f"fixed tiling {tiling}: |u - u_ref| / |u_ref| = {err:.2e}, {its} vs {its_o} preconditioner calls")
+    assert err <= 2e-5, (err, its, its_o)
 
 
 def test_solve_dense_direct_fp64():
