@@ -195,4 +195,31 @@ __device__ __forceinline__ void reset_ticket(unsigned *counter) {
     __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Sum of a double over the 64 lanes of a wavefront, returned in every lane, in
+// a fixed order.  Lane exchanges use DPP on the two 32-bit halves: xor 1 and
+// xor 2 inside each quad, then rotations by 4 and 8 inside each 16-lane row
+// (every lane then holds its row sum), and the four row sums are read out.
+// All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_double<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_double<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_double<0x124>(v);   // row_ror:4
+    v += dpp_double<0x128>(v);   // row_ror:8
+    const long long b = __double_as_longlong(v);
+    double r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int lo = __builtin_amdgcn_readlane((int)b, 16 * q), hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * q);
+        r[q] = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+    return (r[0] + r[1]) + (r[2] + r[3]);
+}
+
 }  // namespace helm

@@ -267,8 +267,8 @@ __device__ __forceinline__ Z<R> row_value(const LevelArgs<R> &L, const Coef<R> &
 }
 
 __device__ __forceinline__ void block_reduce_store(double v, double *dst) {
-    // wave64 butterfly then across the 4 waves through LDS
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    // wavefront sum (DPP), then across the 4 waves through LDS
+    v = wave_sum_f64(v);
     __shared__ double red[kWavesY];
     int w = threadIdx.y, l = threadIdx.x;
     if (l == 0) red[w] = v;

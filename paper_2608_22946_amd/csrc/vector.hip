@@ -32,10 +32,7 @@ __device__ __forceinline__ D2 cdot(T a, T b) {   // conj(a) * b
     return {ar * br + ai * bi, ar * bi - ai * br};
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
 
 // Block-reduce NS complex sums, store them as this block's partials, then
 // return true in the last block to arrive (which may read every block's partials).
@@ -223,7 +220,8 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
     D2 acc[NV + 1];
 #pragma unroll
     for (int s = 0; s <= NV; ++s) acc[s] = {0, 0};
-#pragma unroll 2
+    // two elements per iteration in flight while the registers allow it
+#pragma unroll (NV <= 6 ? 2 : 1)
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         T v[NV];
         T wi = w[i];
@@ -385,9 +383,12 @@ __global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KStat
     if (!reduce_partials<NS>(acc, rb)) return;
     __shared__ D2 tot[kSlots];
     sum_partials<NS>(rb, tot);
+    // the small dense solve runs on one thread with its arrays in LDS
+    // (dynamically indexed arrays in registers would go to scratch memory)
+    constexpr int m = NP - 1;
+    __shared__ double G[NP][NP][2];
+    __shared__ double Lr[m][m], Li[m][m], ur[m], ui[m];
     if (threadIdx.x == 0) {
-        constexpr int m = NP - 1;
-        double G[NP][NP][2];
         int s = 0;
         for (int a = 0; a < NP; ++a)
             for (int b = a; b < NP; ++b) {
@@ -397,7 +398,6 @@ __global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KStat
                 G[b][a][1] = -tot[s].i;
                 ++s;
             }
-        double Lr[m][m], Li[m][m];
         int rank = m;
         for (int j = 0; j < m && rank == m; ++j) {
             double d = G[j + 1][j + 1][0];
@@ -419,7 +419,6 @@ __global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KStat
                 Li[i][j] = ai / ljj;
             }
         }
-        double ur[m], ui[m];
         for (int i = 0; i < rank; ++i) {   // L u = rhs, rhs_i = <P_{i+1}, P_0>
             double ar = G[i + 1][0][0], ai = G[i + 1][0][1];
             for (int k = 0; k < i; ++k) {
@@ -545,8 +544,10 @@ __global__ void __launch_bounds__(256) k_velocity_check(const float *__restrict_
 }
 
 // 256 blocks of 1024 threads (one per CU, 16 wavefronts), fewer only for tiny vectors
+// blocks of a reduction: at least ~4 elements per thread, so that small (cache
+// resident) vectors spend their time on loads rather than on block reductions
 int red_blocks(long long n) {
-    long long b = (n + 2 * kRedThreads - 1) / (2 * kRedThreads);
+    long long b = (n + 4 * kRedThreads - 1) / (4 * kRedThreads);
     if (b < 1) b = 1;
     if (b > 256) b = 256;
     return (int)b;
