@@ -272,11 +272,13 @@ struct Eng {
     }
 
     // Arnoldi step: V[k+1] <- A Z[k] orthonormalised against V[0..k] (CGS2), Givens update of column k
-    hipError_t arnoldi(int l, T **V, int k, KState *st) {
+    // The last step of a cycle (last = true) stops after the Hessenberg column:
+    // the next basis vector is never used, so it is neither written nor normalised.
+    hipError_t arnoldi(int l, T **V, int k, KState *st, bool last) {
         HIP_CHK(launch_dots<T>((const T *const *)V, k + 1, V[k + 1], false, nn(l), EPI_ARNOLDI1, st, k, nullptr, H->rb,
                                s));
-        HIP_CHK(launch_axpy_dots<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, H->rb, s));
-        HIP_CHK(launch_axpy_scale<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, s));
+        HIP_CHK(launch_axpy_dots<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, H->rb, s, !last));
+        if (!last) HIP_CHK(launch_axpy_scale<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, s));
         return hipSuccess;
     }
 
@@ -297,7 +299,7 @@ struct Eng {
             for (int k = 0; k < m; ++k) {
                 HIP_CHK(prec(V[k], Zp[k]));
                 HIP_CHK(stencil(l, M_APPLY, shifted, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
-                HIP_CHK(arnoldi(l, V, k, st));
+                HIP_CHK(arnoldi(l, V, k, st, k == m - 1));
             }
             HIP_CHK((launch_combine<T, T>(x, (const T *const *)Zp, m, nn(l), st, true, from_zero, s)));
         }
@@ -416,7 +418,7 @@ struct Eng {
                 HIP_TRY(precond(V[k], Zp[k]));
                 ++its;
                 HIP_TRY(stencil(0, M_APPLY, false, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
-                HIP_TRY(arnoldi(0, V, k, st));
+                HIP_TRY(arnoldi(0, V, k, st, k == o.m_out - 1));
                 HIP_TRY(read_state(st));
                 kk = k + 1;
                 const KState &hs = *H->host_state;

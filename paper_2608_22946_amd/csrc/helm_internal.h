@@ -131,7 +131,7 @@ hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long lo
 
 template <typename T>
 hipError_t launch_axpy_dots(const T *const *V, int nv, T *w, long long n, KState *st, const RedBuf &rb,
-                            hipStream_t s);
+                            hipStream_t s, bool store = true);
 
 template <typename T>
 hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KState *st, hipStream_t s);

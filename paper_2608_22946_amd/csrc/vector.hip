@@ -201,8 +201,10 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
     }
 }
 
-// w <- w - sum_j h1_j V_j; then conj(V_j) w and ||w||^2; Givens update of column NV-1
-template <typename T, int NV>
+// w <- w - sum_j h1_j V_j; then conj(V_j) w and ||w||^2; Givens update of column NV-1.
+// Without STORE the corrected w is not written back: the last Arnoldi step of a
+// cycle needs only the Hessenberg column and h_{k+1,k}, not the next basis vector.
+template <typename T, int NV, bool STORE>
 __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict__ w, long long n, KState *st,
                                                   RedBuf rb) {
     __shared__ double hs[NV][2];
@@ -231,7 +233,7 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
             wi.re -= hr[j] * v[j].re - hi[j] * v[j].im;
             wi.im -= hr[j] * v[j].im + hi[j] * v[j].re;
         }
-        w[i] = wi;
+        if (STORE) w[i] = wi;
 #pragma unroll
         for (int j = 0; j < NV; ++j) acc[j] = acc[j] + cdot(v[j], wi);
         acc[NV] = acc[NV] + D2{(double)wi.re * wi.re + (double)wi.im * wi.im, 0.0};
@@ -608,10 +610,17 @@ hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long lo
 
 template <typename T>
 hipError_t launch_axpy_dots(const T *const *V, int nv, T *w, long long n, KState *st, const RedBuf &rb,
-                            hipStream_t s) {
+                            hipStream_t s, bool store) {
     const int nb = red_blocks(n);
-#define HELM_AD(NV) \
-    case NV: hipLaunchKernelGGL((k_axpy_dots<T, NV>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, st, rb); break;
+#define HELM_AD(NV)                                                                                                \
+    case NV:                                                                                                       \
+        if (store)                                                                                                 \
+            hipLaunchKernelGGL((k_axpy_dots<T, NV, true>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, \
+                               st, rb);                                                                            \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_axpy_dots<T, NV, false>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w,  \
+                               n, st, rb);                                                                         \
+        break;
     switch (nv) {
         HELM_AD(1) HELM_AD(2) HELM_AD(3) HELM_AD(4) HELM_AD(5) HELM_AD(6) HELM_AD(7) HELM_AD(8) HELM_AD(9)
         HELM_AD(10) HELM_AD(11) HELM_AD(12)
@@ -710,7 +719,7 @@ hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, 
     template hipError_t launch_dots<T>(const T *const *, int, const T *, bool, long long, int, KState *, int,     \
                                        double *, const RedBuf &, hipStream_t);                                    \
     template hipError_t launch_axpy_dots<T>(const T *const *, int, T *, long long, KState *, const RedBuf &,      \
-                                            hipStream_t);                                                         \
+                                            hipStream_t, bool);                                                   \
     template hipError_t launch_axpy_scale<T>(const T *const *, int, T *, long long, KState *, hipStream_t);       \
     template hipError_t launch_scale<T>(const T *, T *, long long, const KState *, hipStream_t);                  \
     template hipError_t launch_gram<T>(const T *const *, int, long long, KState *, const RedBuf &, hipStream_t); \
