@@ -33,6 +33,7 @@ struct helm_hierarchy {
     LevelArgs<double> Ld[3];
     // device buffers carved from the caller's workspace
     float *vel[3];
+    void *dinv[3][2];    // D^-1 of A_l and B_l per level, in the working precision
     float *wf[3][3];
     double *wd[3][3];
     float *atab_f, *btab_f;
@@ -110,6 +111,7 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     helm_hierarchy *Hp = H ? H : &dummy;
     for (int l = 0; l < 3; ++l) {
         Hp->vel[l] = c.take<float>(g[l].nn);
+        for (int sh = 0; sh < 2; ++sh) Hp->dinv[l][sh] = vec(l);
         for (int a = 0; a < 3; ++a) {
             Hp->wf[l][a] = c.take<float>(6 * (size_t)(g[l].n[a] + 1));
             Hp->wd[l][a] = c.take<double>(6 * (size_t)(g[l].n[a] + 1));
@@ -235,6 +237,10 @@ void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, con
     L.sigma = (R)H->opt.sigma;
     L.tz = 0;
     L.split = 0;
+    // D^-1 exists in the working precision only (the other LevelArgs serve the
+    // FP64 outer residual and Q_h, which do not use it)
+    const bool own = (sizeof(R) == sizeof(double)) == (H->prec == HELM_FP64);
+    for (int sh = 0; sh < 2; ++sh) L.dinv[sh] = own ? static_cast<const R *>(H->dinv[l][sh]) : nullptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -688,6 +694,12 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
         fill_level_args<float>(H, l, H->Lf[l], H->wf[l][0], H->wf[l][1], H->wf[l][2], H->atab_f, H->btab_f);
         fill_level_args<double>(H, l, H->Ld[l], H->wd[l][0], H->wd[l][1], H->wd[l][2], H->atab_d, H->btab_d);
     }
+    for (int l = 0; l < 3; ++l)
+        for (int sh = 0; sh < 2; ++sh) {
+            e = (H->prec == HELM_FP64) ? launch_dinv<double>(H->Ld[l], sh, static_cast<double *>(H->dinv[l][sh]), s)
+                                       : launch_dinv<float>(H->Lf[l], sh, static_cast<float *>(H->dinv[l][sh]), s);
+            if (e != hipSuccess) return bail(HELM_EHIP, std::string("diagonal: ") + hipGetErrorString(e));
+        }
     if ((e = tune_tiles(H)) != hipSuccess) return bail(HELM_EHIP, std::string("tile tuning: ") + hipGetErrorString(e));
     *out = H;
     return HELM_OK;

@@ -55,6 +55,7 @@ struct LevelArgs {
     R sigma;
     int tz;              // z planes per wavefront in the stencil kernels (0: default rule)
     int split;           // 1: stencils run as an interior launch plus a border launch where the tiling allows
+    const R *dinv[2];    // per node D^-1 of A_l ([0]) and B_l ([1]), complex interleaved; 0 on the boundary
 };
 
 // ---------------------------------------------------------------------------
@@ -156,6 +157,8 @@ hipError_t launch_add(const T *x, T *y, long long n, hipStream_t s);   // y += x
 
 template <typename R, typename T>
 hipError_t launch_jac1(const LevelArgs<R> &L, int shifted, double omegaJ, const T *g, T *y, hipStream_t s);
+template <typename R>
+hipError_t launch_dinv(const LevelArgs<R> &L, int shifted, R *out, hipStream_t s);   // out = D^-1 per node
 
 int stencil_blocks(int nx, int ny, int nz, int tz);   // grid size of launch_stencil on a level (tz 0: default)
 constexpr int kTzCandidates[] = {2, 4, 8, 16, 32, 64};

@@ -136,6 +136,7 @@ struct Plane {
     Z<R> p0, p1, p2;   // centre, 4 in-plane face neighbours, 4 in-plane corners
     Z<R> ea, eb;       // x/y stiffness partials (tensor form only)
     Z<R> gc;           // right-hand side at the centre (residual / Jacobi modes)
+    Z<R> dc;           // D^-1 at the centre (Jacobi modes)
     float cc;          // velocity at the centre
 };
 
@@ -338,32 +339,32 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
                    ep = (unsigned)(yp * (int)L.sx + xc);
     const unsigned bx0 = e0 * sizeof(TX), bxm = em * sizeof(TX), bxp = ep * sizeof(TX);
     const unsigned bg0 = e0 * sizeof(TG), bgm = em * sizeof(TG), bgp = ep * sizeof(TG);
-    const unsigned bc0 = e0 * 4u, bcm = em * 4u, bcp = ep * 4u;
+    const unsigned bc0 = e0 * 4u;
     const bool rm_ok = x_int && (yg - 1 >= 1);
     const bool r0_ok = x_int && (yg >= 1) && (yg <= L.ny - 1);
     const bool rp_ok = x_int && (yg + 1 <= L.ny - 1);
 
     Z<R> wx[3] = {{0, 0}, {0, 0}, {0, 0}}, wy[3] = {{0, 0}, {0, 0}, {0, 0}};
-    Z<R> wyc_m = {0, 0}, wyc_p = {0, 0};
     {
         const R *w = L.wx + 6 * xc;
         wx[0] = {w[0], w[1]}; wx[1] = {w[2], w[3]}; wx[2] = {w[4], w[5]};
         const R *v = L.wy + 6 * yg;
         wy[0] = {v[0], v[1]}; wy[1] = {v[2], v[3]}; wy[2] = {v[4], v[5]};
-        if (JAC) {
-            wyc_m = {L.wy[6 * ym + 2], L.wy[6 * ym + 3]};
-            wyc_p = {L.wy[6 * yp + 2], L.wy[6 * yp + 3]};
-        }
     }
     const Z<R> zero = {0, 0};
 
     // Raw loads of one plane (issued one plane ahead of their use).
+    using DT = cplx<R>;
     struct Raw {
         TX va, vb, vc;     // operand rows (or the right-hand side rows in the Jacobi modes)
         TG gb;             // right-hand side at the centre
-        float ca, cb, cc;  // velocity rows (ca, cc only in the Jacobi modes)
+        DT da, db, dc;     // D^-1 rows (Jacobi modes; db alone in the sweep mode)
+        float cb;          // velocity at the centre
         int zp;
     };
+    constexpr bool SWEEP = (MODE == M_JSWEEP);
+    const DT *dinv = reinterpret_cast<const DT *>(L.dinv[SHIFT ? 1 : 0]);
+    const unsigned bd0 = e0 * (unsigned)sizeof(DT), bdm = em * (unsigned)sizeof(DT), bdp = ep * (unsigned)sizeof(DT);
     // Planes past the tile's last plane z1 are re-read from z1 (a cache hit):
     // the prefetch is then issued unconditionally, which keeps the count of
     // outstanding loads the same on every path through the loop, so waiting
@@ -380,13 +381,16 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
             r.vb = at_byte(xp, bx0);
             r.vc = at_byte(xp, bxp);
             if (NEED_G) r.gb = at_byte(plane_ptr(g, L.sy, zc), bg0);
+            if (SWEEP) r.db = at_byte(plane_ptr(dinv, L.sy, zc), bd0);
         } else {
             const TG *gp = plane_ptr(g, L.sy, zc);
             r.va = at_byte(gp, bgm);
             r.vb = at_byte(gp, bg0);
             r.vc = at_byte(gp, bgp);
-            r.ca = at_byte(cp, bcm);
-            r.cc = at_byte(cp, bcp);
+            const DT *dp = plane_ptr(dinv, L.sy, zc);
+            r.da = at_byte(dp, bdm);
+            r.db = at_byte(dp, bd0);
+            r.dc = at_byte(dp, bdp);
         }
     };
     // mask boundary / out-of-box values and form the plane partials
@@ -399,23 +403,17 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
             if (NEED_G) gc = {(R)r.gb.re, (R)r.gb.im};
         } else {
             // fused two-sweep Jacobi: the operand is y1 = omega D^-1 g at every loaded node
-            const int zc = min(max(zp, 0), L.nz);
-            const R *wzp = L.wz + 6 * zc;
-            const Z<R> wxz = zadd(wx[1], Z<R>{wzp[2], wzp[3]});
-            const Coef<R> fa = coef_at(L, stab, r.ca), fb = coef_at(L, stab, r.cb), fc = coef_at(L, stab, r.cc);
-            const Z<R> Da = diag_of<R, SHIFT>(L, fa.a1, fa.a4, fa.k2, zadd(wxz, wyc_m));
-            const Z<R> Db = diag_of<R, SHIFT>(L, fb.a1, fb.a4, fb.k2, zadd(wxz, wy[1]));
-            const Z<R> Dc = diag_of<R, SHIFT>(L, fc.a1, fc.a4, fc.k2, zadd(wxz, wyc_p));
             gc = b;
-            a = zscale(omegaJ, zdiv(a, Da));
-            b = zscale(omegaJ, zdiv(b, Db));
-            c = zscale(omegaJ, zdiv(c, Dc));
+            a = zscale(omegaJ, zmul(Z<R>{r.da.re, r.da.im}, a));
+            b = zscale(omegaJ, zmul(Z<R>{r.db.re, r.db.im}, b));
+            c = zscale(omegaJ, zmul(Z<R>{r.dc.re, r.dc.im}, c));
         }
         if (!(zok && rm_ok)) a = zero;
         if (!(zok && r0_ok)) b = zero;
         if (!(zok && rp_ok)) c = zero;
         P.cc = r.cb;
         P.gc = gc;
+        if (JAC || SWEEP) P.dc = Z<R>{r.db.re, r.db.im};
         plane_partials<R, XI, YI>(a, b, c, wx, wy, P);
     };
 
@@ -435,8 +433,7 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
             } else if (MODE == M_RESID) {
                 res = zsub(o.gc, Hv);
             } else {
-                const Z<R> D = diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, zadd(wx[1], zadd(wy[1], wz[1])));
-                res = zadd(o.p0, zscale(omegaJ, zdiv(zsub(o.gc, Hv), D)));   // p0: operand / y1
+                res = zadd(o.p0, zscale(omegaJ, zmul(o.dc, zsub(o.gc, Hv))));   // p0: operand / y1
             }
         }
         TY *yp_ = const_cast<TY *>(plane_ptr(y, L.sy, z));
@@ -670,8 +667,23 @@ __global__ void __launch_bounds__(256) k_diag(LevelArgs<R> L, const T *__restric
 }
 
 // one Jacobi sweep from zero: y = omega D^-1 g (eq. jacobi-map with n_J = 1)
-template <typename R, typename T, bool SHIFT>
-__global__ void __launch_bounds__(256) k_jac1(LevelArgs<R> L, const T *__restrict__ g, T *__restrict__ y, R omegaJ) {
+template <typename R, typename T>
+__global__ void __launch_bounds__(256) k_jac1(const R *__restrict__ dinv, const T *__restrict__ g, T *__restrict__ y,
+                                              long long nn, R omegaJ) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
+        const Z<R> r = zscale(omegaJ, zmul(Z<R>{dinv[2 * i], dinv[2 * i + 1]}, ld<R>(g, i)));
+        T o;
+        o.re = r.r;
+        o.im = r.i;
+        y[i] = o;
+    }
+}
+
+// D^-1 at every node of a level (zero on the boundary): the diagonal depends
+// only on the velocity, the stretching and the shift, so the Jacobi kernels
+// read it instead of evaluating the coefficients of every neighbour row.
+template <typename R, bool SHIFT>
+__global__ void __launch_bounds__(256) k_dinv(LevelArgs<R> L, R *__restrict__ out) {
     extern __shared__ unsigned char smem_raw[];
     R *stab = reinterpret_cast<R *>(smem_raw);
     for (int i = threadIdx.x; i < L.K * 20; i += blockDim.x) stab[i] = L.atab[i];
@@ -686,12 +698,10 @@ __global__ void __launch_bounds__(256) k_jac1(LevelArgs<R> L, const T *__restric
             Coef<R> cf = coef_at(L, stab, L.c[i]);
             Z<R> ws = {L.wx[6 * xi + 2] + L.wy[6 * yi + 2] + L.wz[6 * zi + 2],
                        L.wx[6 * xi + 3] + L.wy[6 * yi + 3] + L.wz[6 * zi + 3]};
-            r = zscale(omegaJ, zdiv(ld<R>(g, i), diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, ws)));
+            r = zdiv(Z<R>{1, 0}, diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, ws));
         }
-        T o;
-        o.re = r.r;
-        o.im = r.i;
-        y[i] = o;
+        out[2 * i] = r.r;
+        out[2 * i + 1] = r.i;
     }
 }
 
@@ -751,6 +761,9 @@ hipError_t launch_stencil_part(const LevelArgs<R> &L, const StencilCall &c, cons
 
 template <typename R, typename TX, typename TG, typename TY>
 hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, hipStream_t s) {
+    // the Jacobi modes read the stored D^-1 of the operator
+    if ((c.mode == M_JSWEEP || c.mode == M_JAC2 || c.mode == M_JAC2_ADD) && !L.dinv[c.shifted ? 1 : 0])
+        return hipErrorInvalidValue;
     TileMap M;
     M.ntx = x_tiles(L);
     M.nty = ceil_div(L.ny + 1, kWavesY);
@@ -802,15 +815,26 @@ hipError_t launch_diag(const LevelArgs<R> &L, int shifted, const T *x, T *y, hip
 
 template <typename R, typename T>
 hipError_t launch_jac1(const LevelArgs<R> &L, int shifted, double omegaJ, const T *g, T *y, hipStream_t s) {
+    const R *dinv = L.dinv[shifted ? 1 : 0];
+    if (!dinv) return hipErrorInvalidValue;
+    const long long nn = (long long)(L.nz + 1) * L.sy;
+    int blocks = (int)std::min<long long>((nn + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_jac1<R, T>), dim3(blocks), dim3(256), 0, s, dinv, g, y, nn, (R)omegaJ);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dinv(const LevelArgs<R> &L, int shifted, R *out, hipStream_t s) {
     const long long nn = (long long)(L.nz + 1) * L.sy;
     int blocks = (int)std::min<long long>((nn + 255) / 256, 65536);
     if (shifted)
-        hipLaunchKernelGGL((k_jac1<R, T, true>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, g, y, (R)omegaJ);
+        hipLaunchKernelGGL((k_dinv<R, true>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, out);
     else
-        hipLaunchKernelGGL((k_jac1<R, T, false>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, g, y,
-                           (R)omegaJ);
+        hipLaunchKernelGGL((k_dinv<R, false>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, out);
     return hipGetLastError();
 }
+template hipError_t launch_dinv<float>(const LevelArgs<float> &, int, float *, hipStream_t);
+template hipError_t launch_dinv<double>(const LevelArgs<double> &, int, double *, hipStream_t);
 
 template hipError_t launch_jac1<float, c32>(const LevelArgs<float> &, int, double, const c32 *, c32 *, hipStream_t);
 template hipError_t launch_jac1<double, c64>(const LevelArgs<double> &, int, double, const c64 *, c64 *, hipStream_t);
