@@ -278,11 +278,14 @@ struct Eng {
     }
 
     // Arnoldi step: V[k+1] <- A Z[k] orthonormalised against V[0..k] (CGS2), Givens update of column k
-    // The last step of a cycle (last = true) stops after the Hessenberg column:
-    // the next basis vector is never used, so it is neither written nor normalised.
+    // Classical Gram-Schmidt with a second pass only where the first one lost
+    // more than half of ||w||^2 (decided on the device: the second-pass kernel
+    // returns at once otherwise).  The last step of a cycle (last = true) stops
+    // after the Hessenberg column: the next basis vector is never used, so it is
+    // neither written nor normalised.
     hipError_t arnoldi(int l, T **V, int k, KState *st, bool last) {
-        HIP_CHK(launch_dots<T>((const T *const *)V, k + 1, V[k + 1], false, nn(l), EPI_ARNOLDI1, st, k, nullptr, H->rb,
-                               s));
+        HIP_CHK(launch_dots<T>((const T *const *)V, k + 1, V[k + 1], true, nn(l), EPI_ARNOLDI_SEL, st, k, nullptr,
+                               H->rb, s));
         HIP_CHK(launch_axpy_dots<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, H->rb, s, !last));
         if (!last) HIP_CHK(launch_axpy_scale<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, s));
         return hipSuccess;

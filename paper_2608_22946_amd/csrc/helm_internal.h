@@ -75,7 +75,7 @@ struct KState {
     int kk;                          // Arnoldi columns in the current cycle
     int breakdown;
     int nonfinite;
-    int pad;
+    int reorth;                      // 1: the newest column needs the second Gram-Schmidt pass
 };
 
 struct RedBuf {
@@ -90,7 +90,9 @@ enum Epi {
     EPI_NORM_INIT = 1,   // beta = sqrt(norm); reset the Krylov state; scale = 1/beta
     EPI_ARNOLDI1 = 2,    // h1 = dots
     EPI_ARNOLDI2 = 3,    // h = h1 + h2, subdiagonal, Givens update of column k
-    EPI_GRAM = 4         // s-step Gram matrix -> least-squares coefficients y
+    EPI_GRAM = 4,        // s-step Gram matrix -> least-squares coefficients y
+    EPI_ARNOLDI_SEL = 5  // h1 = dots with ||w||^2; one pass suffices when ||w - V h1||^2 >= ||w||^2 / 2
+                         // (then Givens update now, h2 = h1, reorth = 0), else reorth = 1
 };
 
 // ---------------------------------------------------------------------------

@@ -194,6 +194,28 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
                 st->h1[j][0] = tot[j].r;
                 st->h1[j][1] = tot[j].i;
             }
+            st->reorth = 1;
+        } else if (EPI == EPI_ARNOLDI_SEL && NV > 0) {
+            // Kahan-Parlett "twice is enough": if the first projection keeps at
+            // least half of ||w||^2, w - V h1 is orthogonal to working accuracy
+            // and the second pass is skipped.
+            double c2 = 0.0;
+            for (int j = 0; j < NV; ++j) {
+                st->h1[j][0] = tot[j].r;
+                st->h1[j][1] = tot[j].i;
+                c2 += tot[j].r * tot[j].r + tot[j].i * tot[j].i;
+            }
+            const double w2 = tot[NS - 1].r, r2 = w2 - c2;
+            if (r2 >= 0.5 * w2) {
+                for (int j = 0; j < NV; ++j) {
+                    st->h2[j][0] = tot[j].r;
+                    st->h2[j][1] = tot[j].i;
+                }
+                st->reorth = 0;
+                givens_column(st, NV - 1, tot, sqrt(r2));
+            } else {
+                st->reorth = 1;
+            }
         } else if (EPI == EPI_NORM_INIT) {
             state_init(st, sqrt(tot[NS - 1].r));
         }
@@ -207,6 +229,7 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
 template <typename T, int NV, bool STORE>
 __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict__ w, long long n, KState *st,
                                                   RedBuf rb) {
+    if (!st->reorth) return;   // the first pass was enough (the whole grid returns; no ticket is taken)
     __shared__ double hs[NV][2];
     if (threadIdx.x < NV) {
         hs[threadIdx.x][0] = st->h1[threadIdx.x][0];
@@ -545,7 +568,6 @@ __global__ void __launch_bounds__(256) k_velocity_check(const float *__restrict_
     }
 }
 
-// 256 blocks of 1024 threads (one per CU, 16 wavefronts), fewer only for tiny vectors
 // blocks of a reduction: at least ~4 elements per thread, so that small (cache
 // resident) vectors spend their time on loads rather than on block reductions
 int red_blocks(long long n) {
@@ -585,6 +607,9 @@ hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long lo
             else if (epi == EPI_NORM_INIT)                                                                          \
                 hipLaunchKernelGGL((k_dots<T, NV, true, EPI_NORM_INIT>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), \
                                    w, n, st, out, rb);                                                              \
+            else if (epi == EPI_ARNOLDI_SEL && NV > 0)                                                              \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_ARNOLDI_SEL>), dim3(nb), dim3(kRedThreads), 0, s,         \
+                                   pack<T, NV>(V), w, n, st, out, rb);                                              \
             else                                                                                                    \
                 return hipErrorInvalidValue;                                                                        \
         } else {                                                                                                    \
