@@ -152,6 +152,15 @@ helm_status helm_jacobi(helm_hierarchy *H, int level, int op, const void *g, int
 /* coarse = R fine (full weighting), fine on `level` (0 or 1), coarse on level+1. */
 helm_status helm_restrict(helm_hierarchy *H, int level, const void *fine, void *coarse);
 
+/* coarse = R (g - op x): the residual on `level` (0 or 1) restricted by full
+ * weighting to level+1 in one fused pass over the fine grid plus a small pass
+ * over a quarter-size intermediate held in the workspace (eq. full-weighting
+ * applied to the residual, as in steps 2 of Algorithm 1 and of
+ * eq. shifted-auxiliary-cycle).  op = HELM_OP_A or HELM_OP_B; g, x on level,
+ * coarse on level+1 (boundary entries written as zero); coarse must not alias
+ * g or x.  Returns HELM_EINVAL for other levels or ops. */
+helm_status helm_residual_restrict(helm_hierarchy *H, int level, int op, const void *g, const void *x, void *coarse);
+
 /* fine += P coarse (trilinear), coarse on `level` (1 or 2), fine on level-1. */
 helm_status helm_prolong_add(helm_hierarchy *H, int level, const void *coarse, void *fine);
 

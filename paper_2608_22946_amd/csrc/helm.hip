@@ -46,6 +46,7 @@ struct helm_hierarchy {
     void *P4[kM4Max + 1], *Z4[kM4Max];
     void *e4;
     void *tmp[3];
+    void *wrest[2];      // x/z-restricted residual rows (fused residual + full weighting from level l)
     KState *st_outer, *st_smooth, *st_k2h, *st_bottom, *st_hook;
     RedBuf rb;
     double *dscratch;     // small device result buffer (dots, velocity check)
@@ -137,6 +138,8 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     for (int j = 0; j < o.m_4h; ++j) Hp->Z4[j] = vec(2);
     Hp->e4 = vec(2);
     for (int l = 0; l < 3; ++l) Hp->tmp[l] = vec(l);
+    for (int l = 0; l < 2; ++l)
+        Hp->wrest[l] = c.take<char>(es * (size_t)(g[l].n[2] / 2 + 1) * (g[l].n[1] + 1) * (g[l].n[0] / 2 + 1));
     Hp->st_outer = c.take<KState>(1);
     Hp->st_smooth = c.take<KState>(1);
     Hp->st_k2h = c.take<KState>(1);
@@ -235,8 +238,8 @@ void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, con
     L.omega_ell = (R)(H->omega * g.ell);
     L.inv_ell2 = (R)(1.0 / (g.ell * g.ell));
     L.sigma = (R)H->opt.sigma;
-    L.tz = 0;
-    L.split = 0;
+    L.tz[0] = L.tz[1] = 0;
+    L.split[0] = L.split[1] = 0;
     // D^-1 exists in the working precision only (the other LevelArgs serve the
     // FP64 outer residual and Q_h, which do not use it)
     const bool own = (sizeof(R) == sizeof(double)) == (H->prec == HELM_FP64);
@@ -262,6 +265,12 @@ struct Eng {
                        void *y, bool norm = false, KState *st = nullptr) {
         StencilCall c{mode, shifted ? 1 : 0, wJ, x, g, base, y, norm, EPI_NORM_INIT, st, 0};
         return launch_stencil<R, T, T, T>(L(l), c, H->rb, s);
+    }
+
+    // coarse = R (g - op x) from level l to l+1 (eq. full-weighting fused with the residual)
+    hipError_t resid_restrict(int l, bool shifted, const T *x, const T *g, T *coarse) {
+        HIP_CHK(stencil(l, M_RESID_R, shifted, 0.0, x, g, nullptr, H->wrest[l]));
+        return launch_restrict_y<T>(H->geom[l], H->geom[l + 1], static_cast<const T *>(H->wrest[l]), coarse, s);
     }
 
     // y = J_nJ(op, g; w) from zero; tmp is a scratch vector of the level
@@ -339,8 +348,7 @@ struct Eng {
         const helm_options &o = H->opt;
         T *y = v(H->vy), *r = v(H->vr), *q4 = v(H->P4[0]), *e4 = v(H->e4);
         HIP_CHK(jacobi(1, true, o.nJ_2h, o.omega_2h, q, y));                 // y = J(B_2h, q)
-        HIP_CHK(stencil(1, M_RESID, true, 0.0, y, q, nullptr, r));           // q - B y
-        HIP_CHK(launch_restrict<T>(H->geom[1], H->geom[2], r, q4, s));      // q_4h = R(q - B y)
+        HIP_CHK(resid_restrict(1, true, y, q, q4));                          // q_4h = R(q - B y)
         HIP_CHK(bottom(q4, e4));                                             // e_4h = C_4h(q_4h)
         HIP_CHK(launch_prolong_add<T>(H->geom[2], H->geom[1], e4, y, s));   // y~ = y + P e_4h
         HIP_CHK(stencil(1, M_RESID, true, 0.0, y, q, nullptr, r));           // q - B y~
@@ -369,10 +377,9 @@ struct Eng {
 
     // Algorithm 1: z = M_h^{-1} r
     hipError_t precond(const T *r, T *z) {
-        T *t = v(H->Vs[0]), *r2 = v(H->r2), *e2 = v(H->e2);
+        T *r2 = v(H->r2), *e2 = v(H->e2);
         HIP_CHK(smooth(r, z, true));                                          // 1: z_pre = S_h(r; 0)
-        HIP_CHK(stencil(0, M_RESID, false, 0.0, z, r, nullptr, t));          // 2: r_2h = R(r - A z_pre)
-        HIP_CHK(launch_restrict<T>(H->geom[0], H->geom[1], t, r2, s));
+        HIP_CHK(resid_restrict(0, false, z, r, r2));                         // 2: r_2h = R(r - A z_pre)
         HIP_CHK(k2h(r2, e2));                                                 // 3: e_2h = K_2h(r_2h)
         HIP_CHK(launch_prolong_add<T>(H->geom[1], H->geom[0], e2, z, s));    // 4: z~ = z_pre + P e_2h
         HIP_CHK(smooth(r, z, false));                                         // 5: z = S_h(r; z~)
@@ -497,14 +504,15 @@ helm_status dispatch(helm_hierarchy *H, F &&f) {
 
 bool level_ok(int l) { return l >= 0 && l <= 2; }
 
-// Pick, per level, the number of z planes each stencil wavefront marches
-// through and whether the stencils run as one launch or as interior + border
-// launches: time an operator apply plus a fused Jacobi pair (HIP events on the
-// caller's stream, best of two trials) for every candidate and keep the fastest.  Long marches amortise the plane
-// pipeline; short ones give small grids enough workgroups; the split costs a
-// second launch but lets interior tiles run at higher occupancy.
+// Pick, per level and kernel family, the number of z planes each stencil
+// wavefront marches through and whether the stencils run as one launch or as
+// interior + border launches: time the family's kernel (an operator apply, or a
+// fused two-sweep Jacobi) with HIP events on the caller's stream, best of two
+// trials, for every candidate and keep the fastest.  Long marches amortise the
+// plane pipeline; short ones give small grids enough workgroups; the split
+// costs a second launch but lets interior tiles run at higher occupancy.
 template <typename T>
-hipError_t tune_level_tiles(helm_hierarchy *H, int l) {
+hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     Eng<T> E(H);
     T *x = static_cast<T *>(H->tmp[l]);
     T *y = static_cast<T *>(l == 0 ? H->Vs[0] : (l == 1 ? H->vy : H->e4));
@@ -515,23 +523,22 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l) {
     float best = 1e30f;
     int best_tz = 0, best_split = 0;
     hipError_t err = hipSuccess;
+    auto run = [&]() -> hipError_t {
+        return fam == 0 ? E.stencil(l, M_APPLY, l > 0, 0.0, x, nullptr, nullptr, y)
+                        : E.stencil(l, M_JAC2, l > 0, H->opt.omega_h, nullptr, x, nullptr, y);
+    };
     for (int cand = 0; cand < 2 * (int)(sizeof(kTzCandidates) / sizeof(int)) && err == hipSuccess; ++cand) {
         const int tz = kTzCandidates[cand / 2], split = cand % 2;
         if (tz > H->geom[l].n[2] + 1 && tz != kTzCandidates[0] && H->opt.tile_tz == 0) break;
         if ((H->opt.tile_tz != 0 && tz != H->opt.tile_tz) || (H->opt.tile_split >= 0 && split != H->opt.tile_split))
             continue;
-        H->Lf[l].tz = H->Ld[l].tz = tz;
-        H->Lf[l].split = H->Ld[l].split = split;
-        // one operator apply plus one fused two-sweep Jacobi: the two stencil kinds the cycle spends most time in
-        auto pair = [&]() -> hipError_t {
-            hipError_t e = E.stencil(l, M_APPLY, l > 0, 0.0, x, nullptr, nullptr, y);
-            return e != hipSuccess ? e : E.stencil(l, M_JAC2, l > 0, H->opt.omega_h, nullptr, x, nullptr, y);
-        };
-        if ((err = pair()) != hipSuccess) break;
+        H->Lf[l].tz[fam] = H->Ld[l].tz[fam] = tz;
+        H->Lf[l].split[fam] = H->Ld[l].split[fam] = split;
+        if ((err = run()) != hipSuccess) break;
         float ms = 1e30f;
         for (int trial = 0; trial < 2 && err == hipSuccess; ++trial) {
             if ((err = hipEventRecord(a, H->s)) != hipSuccess) break;
-            for (int r = 0; r < 3 && err == hipSuccess; ++r) err = pair();
+            for (int r = 0; r < 3 && err == hipSuccess; ++r) err = run();
             if (err != hipSuccess || (err = hipEventRecord(b, H->s)) != hipSuccess) break;
             if ((err = hipEventSynchronize(b)) != hipSuccess) break;
             float t = 0.f;
@@ -547,23 +554,25 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l) {
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    H->Lf[l].tz = H->Ld[l].tz = best_tz;
-    H->Lf[l].split = H->Ld[l].split = best_split;
+    H->Lf[l].tz[fam] = H->Ld[l].tz[fam] = best_tz;
+    H->Lf[l].split[fam] = H->Ld[l].split[fam] = best_split;
     return err;
 }
 
 hipError_t tune_tiles(helm_hierarchy *H) {
     if (H->opt.tile_tz != 0 && H->opt.tile_split >= 0) {
-        for (int l = 0; l < 3; ++l) {
-            H->Lf[l].tz = H->Ld[l].tz = H->opt.tile_tz;
-            H->Lf[l].split = H->Ld[l].split = H->opt.tile_split;
-        }
+        for (int l = 0; l < 3; ++l)
+            for (int f = 0; f < 2; ++f) {
+                H->Lf[l].tz[f] = H->Ld[l].tz[f] = H->opt.tile_tz;
+                H->Lf[l].split[f] = H->Ld[l].split[f] = H->opt.tile_split;
+            }
         return hipSuccess;
     }
-    for (int l = 0; l < 3; ++l) {
-        hipError_t e = (H->prec == HELM_FP64) ? tune_level_tiles<c64>(H, l) : tune_level_tiles<c32>(H, l);
-        if (e != hipSuccess) return e;
-    }
+    for (int l = 0; l < 3; ++l)
+        for (int f = 0; f < 2; ++f) {
+            hipError_t e = (H->prec == HELM_FP64) ? tune_level_tiles<c64>(H, l, f) : tune_level_tiles<c32>(H, l, f);
+            if (e != hipSuccess) return e;
+        }
     return hipSuccess;
 }
 
@@ -768,6 +777,17 @@ helm_status helm_residual(helm_hierarchy *H, int level, int op, const void *g, c
     if (!level_ok(level) || (op != HELM_OP_A && op != HELM_OP_B) || !g || !x || !r || r == x || r == g)
         return fail(H, HELM_EINVAL, "invalid residual arguments");
     return dispatch(H, [&](auto E) { return E.stencil(level, M_RESID, op == HELM_OP_B, 0.0, x, g, nullptr, r); });
+}
+
+helm_status helm_residual_restrict(helm_hierarchy *H, int level, int op, const void *g, const void *x, void *coarse) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (level < 0 || level > 1 || (op != HELM_OP_A && op != HELM_OP_B) || !g || !x || !coarse || coarse == x ||
+        coarse == g)
+        return fail(H, HELM_EINVAL, "invalid residual-restrict arguments");
+    return dispatch(H, [&](auto E) {
+        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
+        return E.resid_restrict(level, op == HELM_OP_B, (const TT *)x, (const TT *)g, (TT *)coarse);
+    });
 }
 
 helm_status helm_jacobi(helm_hierarchy *H, int level, int op, const void *g, int nJ, double omega, void *y) {

@@ -53,8 +53,9 @@ struct LevelArgs {
     R omega_ell;         // omega * ell
     R inv_ell2;
     R sigma;
-    int tz;              // z planes per wavefront in the stencil kernels (0: default rule)
-    int split;           // 1: stencils run as an interior launch plus a border launch where the tiling allows
+    // stencil tiling per kernel family ([0] apply / residual / sweep, [1] fused two-sweep Jacobi)
+    int tz[2];           // z planes per wavefront (0: default rule)
+    int split[2];        // 1: an interior launch plus a border launch where the tiling allows
     const R *dinv[2];    // per node D^-1 of A_l ([0]) and B_l ([1]), complex interleaved; 0 on the boundary
 };
 
@@ -83,7 +84,9 @@ struct RedBuf {
     unsigned *counter;   // zero between kernels
 };
 
-enum Mode { M_APPLY = 0, M_RESID = 1, M_JSWEEP = 2, M_JAC2 = 3, M_JAC2_ADD = 4 };
+// M_RESID_R: residual restricted in x and z on the fly (first pass of the fused
+// residual + full weighting; launch_restrict_y finishes it)
+enum Mode { M_APPLY = 0, M_RESID = 1, M_JSWEEP = 2, M_JAC2 = 3, M_JAC2_ADD = 4, M_RESID_R = 5 };
 
 enum Epi {
     EPI_STORE = 0,       // write sums to out
@@ -125,6 +128,10 @@ hipError_t launch_diag(const LevelArgs<R> &L, int shifted, const T *x, T *y, hip
 template <typename T>
 hipError_t launch_restrict(const Geom &fine, const Geom &coarse, const T *f, T *c, hipStream_t s);
 
+// second pass of the fused residual + full weighting: coarse = y-weights of the
+// x/z-restricted residual rows w ([coarse z][fine y][coarse x]); zero on the coarse boundary
+template <typename T>
+hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, T *c, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, T *f, hipStream_t s);
 

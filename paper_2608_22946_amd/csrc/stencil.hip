@@ -329,8 +329,10 @@ __device__ __forceinline__ T at_byte(const T *plane, unsigned off) {
 template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM, bool XI, bool YI>
 __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, const TX *__restrict__ x,
                                       const TG *__restrict__ g, const TY *__restrict__ base, TY *__restrict__ y,
-                                      R omegaJ, int xg, int yg, int z0, int z1, bool out_lane, double &nrm) {
+                                      R omegaJ, int xg, int yg, int z0, int z1, bool out_lane, double &nrm,
+                                      int Z0 = 0) {
     constexpr bool JAC = (MODE == M_JAC2 || MODE == M_JAC2_ADD);
+    constexpr bool RESTRICT = (MODE == M_RESID_R);
     constexpr bool NEED_G = (MODE != M_APPLY);
     const bool x_int = (xg >= 1 && xg <= L.nx - 1);
     const int xc = min(max(xg, 0), L.nx);
@@ -418,6 +420,12 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
     };
 
     const bool yint = (yg >= 1 && yg <= L.ny - 1);
+    // M_RESID_R: x/z-restricted residual rows w[coarse z][fine y][coarse x]
+    const int nxc = L.nx >> 1, nzc = L.nz >> 1;
+    const long long wsx = nxc + 1, wsy = (long long)(L.ny + 1) * wsx;
+    const int lane = threadIdx.x;
+    const bool rstore = RESTRICT && (lane & 1) && lane >= 3 && lane <= 61 && yint && (xg >> 1) >= 1 && (xg >> 1) <= nxc - 1;
+    Z<R> rcur = zero;
     // output plane z from planes m, o, p
     auto emit = [&](int z, const Plane<R> &m, const Plane<R> &o, const Plane<R> &p) {
         Z<R> res = zero;
@@ -430,11 +438,34 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
             const Z<R> Hv = row_value<R, XI && YI, SHIFT>(L, cf, m, o, p, zint, wz);
             if (MODE == M_APPLY) {
                 res = Hv;
-            } else if (MODE == M_RESID) {
+            } else if (MODE == M_RESID || RESTRICT) {
                 res = zsub(o.gc, Hv);
             } else {
                 res = zadd(o.p0, zscale(omegaJ, zmul(o.dc, zsub(o.gc, Hv))));   // p0: operand / y1
             }
+        }
+        if (RESTRICT) {
+            // full weighting along x (this lane's fine x is even on the storing
+            // lanes) and along z (running sums over the coarse planes), stored per
+            // fine row; the y weights follow in a second pass
+            const Z<R> rl = zleft(res), rr = zright(res);
+            const Z<R> rx = {(R)0.25 * (rl.r + rr.r) + (R)0.5 * res.r, (R)0.25 * (rl.i + rr.i) + (R)0.5 * res.i};
+            if (z & 1) {   // odd fine plane: completes coarse plane (z-1)/2, starts (z+1)/2
+                rcur.r += (R)0.25 * rx.r;
+                rcur.i += (R)0.25 * rx.i;
+                const int Zc = (z - 1) >> 1;
+                if (rstore && z >= 2 * Z0 + 1 && Zc >= 1 && Zc <= nzc - 1) {
+                    TY ov;
+                    ov.re = rcur.r;
+                    ov.im = rcur.i;
+                    y[(long long)Zc * wsy + (long long)yg * wsx + (xg >> 1)] = ov;
+                }
+                rcur = {(R)0.25 * rx.r, (R)0.25 * rx.i};
+            } else {
+                rcur.r += (R)0.5 * rx.r;
+                rcur.i += (R)0.5 * rx.i;
+            }
+            return;
         }
         TY *yp_ = const_cast<TY *>(plane_ptr(y, L.sy, z));
         if (MODE == M_JAC2_ADD) {
@@ -552,6 +583,35 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
     }
     const int lane = threadIdx.x;
     const int yg = yt * kWavesY + threadIdx.y;
+    if (MODE == M_RESID_R) {
+        // Fused residual + full weighting, first pass: x tiles of 60 fine columns
+        // (lanes 0..63 hold x = 60 xt - 1 .. 60 xt + 62; the residual is valid on
+        // lanes 1..62, so the odd lanes 3..61 hold the 30 coarse columns whose
+        // three fine neighbours are all valid); z chunks of M.tz coarse planes,
+        // marching fine planes 2 Z0 - 1 .. 2 Z1 - 1 (one odd plane shared with
+        // the next chunk).
+        const int xg = 60 * xt - 1 + lane;
+        const int xa = max(1, 60 * xt), xb = min(60 * xt + 61, L.nx - 1);
+        const bool xi = (xa > xb) || (xa >= L.lox && xb <= L.hix);
+        const int Z0 = zc * M.tz, Z1 = min(Z0 + M.tz, L.nz >> 1);
+        double nrm = 0.0;
+        if (yg <= L.ny) {
+            const bool yi = (yg >= L.loy && yg <= L.hiy) || yg < 1 || yg > L.ny - 1;
+            if (xi && yi)
+                march<R, TX, TG, TY, MODE, SHIFT, false, true, true>(L, stab, x, g, base, y, omegaJ, xg, yg, 2 * Z0 - 1,
+                                                                     2 * Z1, false, nrm, Z0);
+            else if (xi)
+                march<R, TX, TG, TY, MODE, SHIFT, false, true, false>(L, stab, x, g, base, y, omegaJ, xg, yg, 2 * Z0 - 1,
+                                                                      2 * Z1, false, nrm, Z0);
+            else if (yi)
+                march<R, TX, TG, TY, MODE, SHIFT, false, false, true>(L, stab, x, g, base, y, omegaJ, xg, yg, 2 * Z0 - 1,
+                                                                      2 * Z1, false, nrm, Z0);
+            else
+                march<R, TX, TG, TY, MODE, SHIFT, false, false, false>(L, stab, x, g, base, y, omegaJ, xg, yg,
+                                                                       2 * Z0 - 1, 2 * Z1, false, nrm, Z0);
+        }
+        return;
+    }
     const int z0 = zc * M.tz;
     const int z1 = min(z0 + M.tz, L.nz + 1);
     // x tiling: with split edges, tile 0 holds both x edge strips (lanes 0..31:
@@ -752,6 +812,13 @@ hipError_t launch_stencil_part(const LevelArgs<R> &L, const StencilCall &c, cons
     case M_JAC2_ADD:
         if (c.shifted) HELM_LAUNCH(M_JAC2_ADD, true, false); else HELM_LAUNCH(M_JAC2_ADD, false, false);
         break;
+    case M_RESID_R:
+        if constexpr (PART == 0) {
+            if (c.shifted) HELM_LAUNCH(M_RESID_R, true, false); else HELM_LAUNCH(M_RESID_R, false, false);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -765,9 +832,20 @@ hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const Red
     if ((c.mode == M_JSWEEP || c.mode == M_JAC2 || c.mode == M_JAC2_ADD) && !L.dinv[c.shifted ? 1 : 0])
         return hipErrorInvalidValue;
     TileMap M;
+    if (c.mode == M_RESID_R) {
+        if (c.norm) return hipErrorInvalidValue;
+        M.ntx = std::max(1, ceil_div((L.nx >> 1) - 1, 30));
+        M.nty = ceil_div(L.ny + 1, kWavesY);
+        M.tz = std::max(1, (L.tz[0] > 0 ? L.tz[0] : pick_tz(M.ntx, M.nty, L.nz + 1)) / 2);   // coarse planes per chunk
+        M.yt_lo = M.nyi = 0;
+        M.block_offset = 0;
+        M.total_blocks = M.ntx * M.nty * ceil_div(L.nz >> 1, M.tz);
+        return launch_stencil_part<R, TX, TG, TY, 0>(L, c, rb, M, M.total_blocks, s);
+    }
     M.ntx = x_tiles(L);
     M.nty = ceil_div(L.ny + 1, kWavesY);
-    M.tz = L.tz > 0 ? L.tz : pick_tz(M.ntx, M.nty, L.nz + 1);
+    const int fam = (c.mode == M_JAC2 || c.mode == M_JAC2_ADD) ? 1 : 0;
+    M.tz = L.tz[fam] > 0 ? L.tz[fam] : pick_tz(M.ntx, M.nty, L.nz + 1);
     const int nzc = ceil_div(L.nz + 1, M.tz);
     const int blocks = M.ntx * M.nty * nzc;
     // interior y tiles: all kWavesY rows inside [loy, hiy]
@@ -775,7 +853,7 @@ hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const Red
     M.nyi = std::max(0, (L.hiy + 1) / kWavesY - M.yt_lo);
     M.block_offset = 0;
     M.total_blocks = blocks;
-    if (L.split && split_edges(L) && M.ntx > 1 && M.nyi > 0) {
+    if (L.split[fam] && split_edges(L) && M.ntx > 1 && M.nyi > 0) {
         const int bi = (M.ntx - 1) * M.nyi * nzc;
         const int bb = blocks - bi;
         hipError_t e = launch_stencil_part<R, TX, TG, TY, 2>(L, c, rb, M, bb, s);

@@ -44,6 +44,28 @@ __global__ void __launch_bounds__(256) k_restrict(Geom F, Geom C, const T *__res
     c[(long long)Zc * C.sy + (long long)Y * C.sx + X] = o;
 }
 
+// Second pass of the fused residual + full weighting: w[Z][y][X] holds the
+// residual already weighted along x and z; coarse node (X, Y, Z) takes the
+// fine rows 2Y-1, 2Y, 2Y+1 with weights 1/4, 1/2, 1/4.  Coarse boundary nodes
+// are written as zero.
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__restrict__ w, T *__restrict__ c) {
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zc = blockIdx.z;
+    if (X > C.n[0] || Y > C.n[1]) return;
+    real_of<T> sr = 0, si = 0;
+    if (X >= 1 && X <= C.n[0] - 1 && Y >= 1 && Y <= C.n[1] - 1 && Zc >= 1 && Zc <= C.n[2] - 1) {
+        const long long wsx = C.n[0] + 1, wsy = (long long)(F.n[1] + 1) * wsx;
+        const T *p = w + (long long)Zc * wsy + (long long)(2 * Y) * wsx + X;
+        const T a = p[-wsx], b = p[0], d = p[wsx];
+        sr = (real_of<T>)0.25 * (a.re + d.re) + (real_of<T>)0.5 * b.re;
+        si = (real_of<T>)0.25 * (a.im + d.im) + (real_of<T>)0.5 * b.im;
+    }
+    T o;
+    o.re = sr;
+    o.im = si;
+    c[(long long)Zc * C.sy + (long long)Y * C.sx + X] = o;
+}
+
 // one thread per fine node: fine += P coarse.  Along each axis a fine node
 // 2j takes coarse node j with weight 1 and a fine node 2j+1 takes j and j+1
 // with weight 1/2 each; coarse boundary nodes contribute zero.
@@ -102,6 +124,12 @@ hipError_t launch_restrict(const Geom &fine, const Geom &coarse, const T *f, T *
 }
 
 template <typename T>
+hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, T *c, hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict_y<T>), node_grid(coarse), dim3(kTX, kTY), 0, s, fine, coarse, w, c);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, T *f, hipStream_t s) {
     hipLaunchKernelGGL((k_prolong_add<T>), node_grid(fine), dim3(kTX, kTY), 0, s, coarse, fine, c, f);
     return hipGetLastError();
@@ -109,6 +137,8 @@ hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, 
 
 template hipError_t launch_restrict<c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t);
 template hipError_t launch_restrict<c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t);
+template hipError_t launch_restrict_y<c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t);
+template hipError_t launch_restrict_y<c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t);
 template hipError_t launch_prolong_add<c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t);
 template hipError_t launch_prolong_add<c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t);
 

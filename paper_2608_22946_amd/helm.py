@@ -35,7 +35,8 @@ class HelmOptions(ctypes.Structure):
 
 
 EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_grad", "helm_destroy",
-            "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_jacobi", "helm_restrict",
+            "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_residual_restrict", "helm_jacobi",
+            "helm_restrict",
             "helm_prolong_add", "helm_bottom", "helm_vcycle", "helm_coarse_solve", "helm_smooth", "helm_precond",
             "helm_vec_dots", "helm_vec_orthonormalize"]
 
@@ -62,6 +63,7 @@ def lib():
         L.helm_dims.argtypes = [P, I, P]
         L.helm_apply.argtypes = [P, I, I, P, P]
         L.helm_residual.argtypes = [P, I, I, P, P, P]
+        L.helm_residual_restrict.argtypes = [P, I, I, P, P, P]
         L.helm_jacobi.argtypes = [P, I, I, P, I, D, P]
         L.helm_restrict.argtypes = [P, I, P, P]
         L.helm_prolong_add.argtypes = [P, I, P, P]
@@ -195,6 +197,13 @@ class Hierarchy:
         _check(lib().helm_jacobi(self._h, level, op, self._vec(g, level), int(nJ), float(omega),
                                  self._vec(y, level)), self._h)
         return y
+
+    def residual_restrict(self, level, op, g, x, out=None):
+        """coarse = R (g - op x), level 0 or 1 -> level + 1 (fused)."""
+        c = self.empty(level + 1) if out is None else out
+        _check(lib().helm_residual_restrict(self._h, level, op, self._vec(g, level), self._vec(x, level),
+                                            self._vec(c, level + 1)), self._h)
+        return c
 
     def restrict(self, level, fine, out=None):
         c = self.empty(level + 1) if out is None else out

@@ -77,8 +77,16 @@ def test_bad_dims_rejected(L, dims, n_pml):
     assert L.helm_last_error(None)
 
 
+def test_good_tile_options_accepted(L):
+    for tz in (0, 2, 4, 8, 16, 32, 64):
+        for split in (-1, 0, 1):
+            rc, _ = _ws(L, (24, 24, 24), 4, _opts(tile_tz=tz, tile_split=split))
+            assert rc == 0, (tz, split)
+
+
 @pytest.mark.parametrize("field,value", [("m_out", 0), ("m_2h", 13), ("m_4h", 9), ("nJ_h", 0), ("c_2h", 0),
-                                         ("iofd_K", 0), ("omega_2h", -0.1), ("struct_size", 8), ("precision", 7)])
+                                         ("iofd_K", 0), ("omega_2h", -0.1), ("struct_size", 8), ("precision", 7),
+                                         ("tile_tz", 3), ("tile_tz", 128), ("tile_split", 2), ("tile_split", -2)])
 def test_bad_options_rejected(L, field, value):
     rc, _ = _ws(L, (24, 24, 24), 4, _opts(**{field: value}))
     assert rc == -1
@@ -118,5 +126,6 @@ def test_calls_on_null_hierarchy(L):
     rel = np.zeros(1)
     assert L.helm_solve(None, ctypes.c_void_p(8), 1, 1e-6, ctypes.c_void_p(16), its.ctypes.data, rel.ctypes.data) == -1
     assert L.helm_apply(None, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(16)) == -1
+    assert L.helm_residual_restrict(None, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(24)) == -1
     assert L.helm_grad(None, None, 1, 1e-6, None) == -5
     L.helm_destroy(None)

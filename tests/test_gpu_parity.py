@@ -84,6 +84,18 @@ def test_residual(pair, level, op):
     assert rel(r, pair.o.residual(level, op, g.astype(complex), x.astype(complex))) <= pair.tol(1e-12, 1e-6)
 
 
+@pytest.mark.parametrize("level,op", [(0, 0), (0, 1), (1, 1), (1, 0)])
+def test_residual_restrict(pair, level, op):
+    """Fused R (g - op x) against the checker's residual followed by its restriction."""
+    g, x = pair.rand(level, 31 + level), pair.rand(level, 41 + op)
+    c = to_np(pair.g.residual_restrict(level, op, pair.dev(g), pair.dev(x)))
+    ref = pair.o.restrict(level, pair.o.residual(level, op, g.astype(complex), x.astype(complex)))
+    assert rel(c, ref) <= pair.tol(1e-12, 1e-6)
+    # boundary of the coarse vector is exactly zero
+    for ax in range(3):
+        assert np.abs(np.take(c, [0, -1], axis=ax)).max() == 0.0
+
+
 @pytest.mark.parametrize("level,op,nJ,w", [(0, 0, 2, 0.8), (1, 1, 2, 0.8), (2, 1, 2, 0.2), (1, 1, 1, 0.7),
                                            (0, 0, 3, 0.6), (2, 1, 4, 0.2)])
 def test_jacobi(pair, level, op, nJ, w):
@@ -218,6 +230,11 @@ def test_tiling_stencils(tiled):
         g, x = p.rand(level, 410 + level), p.rand(level, 420 + level)
         r = to_np(p.g.residual(level, op, p.dev(g), p.dev(x)))
         assert rel(r, p.o.residual(level, op, g.astype(complex), x.astype(complex))) <= p.tol(1e-12, 1e-6)
+    for level, op in [(0, 0), (1, 1)]:
+        g, x = p.rand(level, 450 + level), p.rand(level, 460 + level)
+        c = to_np(p.g.residual_restrict(level, op, p.dev(g), p.dev(x)))
+        ref = p.o.restrict(level, p.o.residual(level, op, g.astype(complex), x.astype(complex)))
+        assert rel(c, ref) <= p.tol(1e-12, 1e-6)
     for level, op, nJ, w in [(0, 0, 2, 0.8), (0, 0, 3, 0.8), (1, 1, 2, 0.8)]:
         g = p.rand(level, 430 + level + nJ)
         assert rel(to_np(p.g.jacobi(level, op, p.dev(g), nJ, w)), p.o.jacobi(level, op, g.astype(complex), nJ, w)) \
@@ -330,6 +347,20 @@ def test_c2_sampled_apply(c2):
         nodes = rng.integers(0, int(np.prod(shp)), 4096)
         ref = p.o.apply_at(level, op, x.astype(np.complex128), nodes)
         assert rel(y[nodes].astype(np.complex128), ref) <= 1e-6
+
+
+def test_c2_residual_restrict(c2):
+    """Fused R (g - A x) fine -> 2h and R (g - B x) 2h -> 4h at the full size, every coarse node against the
+    checker's residual and restriction."""
+    p, _ = c2
+    rng = np.random.default_rng(6)
+    for level, op in [(0, 0), (1, 1)]:
+        shp = p.g.shape(level)
+        g = (rng.standard_normal(shp, dtype=np.float32) + 1j * rng.standard_normal(shp, dtype=np.float32))
+        x = (rng.standard_normal(shp, dtype=np.float32) + 1j * rng.standard_normal(shp, dtype=np.float32))
+        c = p.g.residual_restrict(level, op, p.dev(g), p.dev(x)).cpu().numpy().astype(np.complex128)
+        ref = p.o.restrict(level, p.o.residual(level, op, g.astype(np.complex128), x.astype(np.complex128)))
+        assert rel(c, ref) <= 1e-6
 
 
 def test_c2_solve_residual(c2):
