@@ -137,6 +137,7 @@ struct Plane {
     Z<R> ea, eb;       // x/y stiffness partials (tensor form only)
     Z<R> gc;           // right-hand side at the centre (residual / Jacobi modes)
     Z<R> dc;           // D^-1 at the centre (Jacobi modes)
+    Z<R> bc;           // base value at the centre (fused Jacobi + base)
     float cc;          // velocity at the centre
 };
 
@@ -361,6 +362,7 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
         TX va, vb, vc;     // operand rows (or the right-hand side rows in the Jacobi modes)
         TG gb;             // right-hand side at the centre
         DT da, db, dc;     // D^-1 rows (Jacobi modes; db alone in the sweep mode)
+        TY bb;             // base at the centre (fused Jacobi + base)
         float cb;          // velocity at the centre
         int zp;
     };
@@ -393,6 +395,7 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
             r.da = at_byte(dp, bdm);
             r.db = at_byte(dp, bd0);
             r.dc = at_byte(dp, bdp);
+            if (MODE == M_JAC2_ADD) r.bb = at_byte(plane_ptr(base, L.sy, zc), e0 * (unsigned)sizeof(TY));
         }
     };
     // mask boundary / out-of-box values and form the plane partials
@@ -416,6 +419,7 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
         P.cc = r.cb;
         P.gc = gc;
         if (JAC || SWEEP) P.dc = Z<R>{r.db.re, r.db.im};
+        if (MODE == M_JAC2_ADD) P.bc = Z<R>{(R)r.bb.re, (R)r.bb.im};
         plane_partials<R, XI, YI>(a, b, c, wx, wy, P);
     };
 
@@ -469,9 +473,8 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
         }
         TY *yp_ = const_cast<TY *>(plane_ptr(y, L.sy, z));
         if (MODE == M_JAC2_ADD) {
-            const TY bv = at_byte(plane_ptr(base, L.sy, z), e0 * (unsigned)sizeof(TY));
-            res.r += (R)bv.re;
-            res.i += (R)bv.im;
+            res.r += o.bc.r;
+            res.i += o.bc.i;
         }
         if (out_lane) {
             TY ov;
