@@ -86,6 +86,85 @@ def cpu_baseline(vel, omega, table, gpu_pc_calls):
                       f"{t_pc:.2f} s; scaled by the GPU solve's {gpu_pc_calls} preconditioner calls"}
 
 
+def green_err(u, N, npml, h, k, src):
+    """Sum of the relative l1 errors of the distance-scaled real and imaginary parts
+    against the outgoing Green function exp(ikr)/(4 pi r) (Sec. 5.1), on the nodes of
+    the physical box whose indices are multiples of 4 and with r >= 2 pi / k."""
+    idx = np.arange(0, N + 1, 4)
+    phys = idx[(idx >= npml) & (idx <= N - npml)]
+    sx, sy, sz = src
+    out = [0.0, 0.0, 0.0, 0.0]
+    for iz in phys:   # one plane at a time keeps the host memory small
+        y, x = np.meshgrid(phys, phys, indexing="ij")
+        r = h * np.sqrt((x - sx) ** 2 + (y - sy) ** 2 + float(iz - sz) ** 2)
+        m = r >= 2 * np.pi / k
+        if not m.any():
+            continue
+        rr = r[m]
+        uh = u[iz][np.ix_(phys, phys)][m].astype(np.complex128)
+        G = np.exp(1j * k * rr) / (4 * np.pi * rr)
+        out[0] += np.abs(rr * (G.real - uh.real)).sum()
+        out[1] += np.abs(rr * G.real).sum()
+        out[2] += np.abs(rr * (G.imag - uh.imag)).sum()
+        out[3] += np.abs(rr * G.imag).sum()
+    return out[0] / out[1] + out[2] / out[3]
+
+
+def paper_table():
+    """The paper's single-GPU results on its own meshes (512^3 total intervals,
+    8 PML cells, 6 points per shortest wavelength, FP32, source at the centre
+    node): the homogeneous Green-function test over the outer tolerances of its
+    tolerance table, and the lens / wedge / barrier media at tol 1e-4.  One JSON
+    line per case, with the paper's A100 numbers beside ours."""
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import barrier_velocity, homogeneous, lens_velocity, load_iofd_table, point_source, wedge_velocity
+    from workloads.configs import omega_for_ppw
+
+    Ntot, npml = 512, 8
+    n = Ntot - 2 * npml
+    h = 1.0 / n                      # physical box [0, 1]^3, normalised media coordinates
+    src = (Ntot // 2,) * 3
+    dev = torch.device("cuda", 0)
+    table = load_iofd_table()
+    f = torch.from_numpy(point_source((Ntot,) * 3, src, h, dtype=np.complex64)).to(dev)
+    paper = {"green": {1e-2: (10, 3.057, 3.3231e-2), 1e-3: (12, 3.606, 1.6226e-2), 1e-4: (19, 5.512, 2.4936e-3),
+                       1e-5: (25, 7.239, 2.7382e-3)},
+             "lens": (12, 4.545), "wedge": (29, 10.863), "barrier": (32, 11.970)}
+    cases = [("green", homogeneous(n, n, n, 1.0), (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)),
+             ("lens", lens_velocity(n, n, n), (1e-4,)), ("wedge", wedge_velocity(n, n, n), (1e-4,)),
+             ("barrier", barrier_velocity(n, n, n), (1e-4,))]
+    for name, vel, tols in cases:
+        omega = omega_for_ppw(float(vel.min()), h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Hh = helm.Hierarchy(torch.from_numpy(vel), h, omega, npml, precision="fp32", table=table, device=dev)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        u = torch.empty_like(f)
+        for tol in tols:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, its, rel, rc = Hh.solve(f, tol, out=u.unsqueeze(0))
+            torch.cuda.synchronize()
+            t_solve = time.perf_counter() - t0
+            line = {"case": name, "mesh": f"{Ntot}^3", "n_pml": npml, "tol": tol, "pc_calls": int(its),
+                    "relres": float(rel), "converged": rc == 0, "t_setup_s": round(t_setup, 3),
+                    "t_solve_s": round(t_solve, 3), "solve_per_pc_s": round(t_solve / max(int(its), 1), 4),
+                    "precision": "fp32"}
+            if name == "green":
+                line["err"] = float(green_err(u.cpu().numpy(), Ntot, npml, h, omega, src))
+                if tol in paper["green"]:
+                    pc, ts, err = paper["green"][tol]
+                    line["paper_a100"] = {"pc_calls": pc, "t_solve_s": ts, "err": err}
+            else:
+                pc, ts = paper[name]
+                line["paper_a100"] = {"pc_calls": pc, "t_solve_s": ts}
+            print(json.dumps(line), flush=True)
+        Hh.close()
+        del Hh
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,11 +174,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-apply", action="store_true",
                     help="only run the fine-level apply loop and a plain copy of the same size (for counters)")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="run the paper's 512^3 Green-function and benchmark-media cases instead (JSON line per case)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see the sharding design).",
               file=sys.stderr)
         sys.exit(2)
+    if args.paper_table:
+        paper_table()
+        return
 
     import torch
     from paper_2608_22946_amd import helm
