@@ -165,6 +165,46 @@ def paper_table():
         del Hh
 
 
+def multi_rhs(lane_counts=(1, 2, 4), seed=3):
+    """Many right-hand sides on one hierarchy: 256^3 + 16-cell PML (288^3 total), a seeded
+    8-layer model (1500..4000 m/s, sharp interfaces), 64 point sources on an 8 x 8 grid in
+    the plane 20 cells below the top of the physical box, FP32, tol 1e-6 per source.
+    One JSON line per lane count (right-hand sides solved concurrently, see helm_options.lanes)."""
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import layered_velocity, load_iofd_table, point_source
+    from workloads.configs import omega_for_ppw
+
+    n, npml = 256, 16
+    N = n + 2 * npml
+    vel = layered_velocity(n, n, n, seed=seed)
+    omega = omega_for_ppw(float(vel.min()), H)
+    dev = torch.device("cuda", 0)
+    table = load_iofd_table()
+    xs = [npml + int(round((i + 0.5) * n / 8)) for i in range(8)]
+    srcs = [(x, y, npml + 20) for y in xs for x in xs]
+    f = torch.from_numpy(np.stack([point_source((N, N, N), s_, H, dtype=np.complex64) for s_ in srcs])).to(dev)
+    for lanes in lane_counts:
+        Hh = helm.Hierarchy(torch.from_numpy(vel), H, omega, npml, precision="fp32", table=table, device=dev,
+                            lanes=lanes)
+        u = torch.empty_like(f)
+        Hh.solve(f[:lanes], TOL, out=u[:lanes])          # warm-up, one source per lane
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, its, rel, rc = Hh.solve(f, TOL, out=u)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"metric": "time-to-rel.res 1e-6 per source, many sources", "value": round(dt / len(srcs), 4),
+                          "unit": "s per source", "lanes": lanes, "sources": len(srcs), "total_s": round(dt, 3),
+                          "pc_calls_mean": float(np.mean(its)), "pc_calls_max": int(np.max(its)),
+                          "max_relres": float(np.max(rel)), "all_converged": rc == 0, "dtype": "f32",
+                          "config": {"workload": "layered-288-fp32: 256^3 + 16-cell PML, 8 seeded layers 1500..4000 "
+                                                 "m/s, 64 point sources on an 8x8 grid 20 cells deep, tol 1e-6",
+                                     "seed": seed}}), flush=True)
+        Hh.close()
+        del Hh, u
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +216,8 @@ def main():
                     help="only run the fine-level apply loop and a plain copy of the same size (for counters)")
     ap.add_argument("--paper-table", action="store_true",
                     help="run the paper's 512^3 Green-function and benchmark-media cases instead (JSON line per case)")
+    ap.add_argument("--multi-rhs", action="store_true",
+                    help="run the 64-source 288^3 layered workload with 1, 2 and 4 concurrent lanes instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see the sharding design).",
@@ -183,6 +225,9 @@ def main():
         sys.exit(2)
     if args.paper_table:
         paper_table()
+        return
+    if args.multi_rhs:
+        multi_rhs()
         return
 
     import torch

@@ -90,6 +90,9 @@ typedef struct {
     int tile_tz;              /* z planes per wavefront: 0 = timed; else 2, 4, 8, 16, 32 or 64 */
     int tile_split;           /* -1 = timed; 0 = one launch per stencil; 1 = an interior launch plus
                                  a border launch where the PML layout allows it */
+    int lanes;                /* right-hand sides helm_solve runs concurrently (1..8; 0 = 1), each on
+                                 its own copy of the solver's vectors and its own stream; the
+                                 workspace grows by one copy per lane */
 } helm_options;
 
 /* Fill *opt with the defaults above (table NULL, stream NULL, FP32). */

@@ -7,10 +7,13 @@
 // (Algorithm 1) needs no host synchronisation.  The host reads one Krylov
 // state per outer Arnoldi step for the convergence test.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "helm_internal.h"
@@ -20,6 +23,30 @@ using namespace helm;
 namespace {
 thread_local std::string g_thread_error;
 }
+
+constexpr int kMaxLanes = 8;   // right-hand sides solved concurrently by helm_solve
+
+// Everything one solve writes: Krylov vectors of the three levels, solver
+// states, reduction buffers, pinned host copies and the stream it runs on.
+struct Lane {
+    void *Vout[kMMax + 1], *Zout[kMMax];
+    void *Vs[kMMax + 1], *Zs[kMMax];
+    c64 *x64, *b64;
+    void *V2[kMMax + 1], *Z2[kMMax];
+    void *e2, *r2, *vy, *vr;
+    void *P4[kM4Max + 1], *Z4[kM4Max];
+    void *e4;
+    void *tmp[3];
+    void *wrest[2];       // x/z-restricted residual rows (fused residual + full weighting from level l)
+    KState *st_outer, *st_smooth, *st_k2h, *st_bottom, *st_hook;
+    RedBuf rb;
+    double *dscratch;     // small device result buffer (dots, velocity check)
+    KState *host_state;   // pinned host copy of a Krylov state
+    double *host_scratch; // pinned host doubles
+    hipStream_t s;        // lane 0: the caller's stream; others: created by helm_setup (default priority)
+    bool own_stream;
+    std::string err;
+};
 
 struct helm_hierarchy {
     helm_options opt;
@@ -31,37 +58,29 @@ struct helm_hierarchy {
     Geom geom[3];
     LevelArgs<float> Lf[3];
     LevelArgs<double> Ld[3];
-    // device buffers carved from the caller's workspace
+    // device buffers carved from the caller's workspace: shared, read-only during solves
     float *vel[3];
     void *dinv[3][2];    // D^-1 of A_l and B_l per level, in the working precision
     float *wf[3][3];
     double *wd[3][3];
     float *atab_f, *btab_f;
     double *atab_d, *btab_d;
-    void *Vout[kMMax + 1], *Zout[kMMax];
-    void *Vs[kMMax + 1], *Zs[kMMax];
-    c64 *x64, *b64;
-    void *V2[kMMax + 1], *Z2[kMMax];
-    void *e2, *r2, *vy, *vr;
-    void *P4[kM4Max + 1], *Z4[kM4Max];
-    void *e4;
-    void *tmp[3];
-    void *wrest[2];      // x/z-restricted residual rows (fused residual + full weighting from level l)
-    KState *st_outer, *st_smooth, *st_k2h, *st_bottom, *st_hook;
-    RedBuf rb;
-    double *dscratch;     // small device result buffer (dots, velocity check)
-    KState *host_state;   // pinned host copy of a Krylov state
-    double *host_scratch; // pinned host doubles
+    int nlanes;
+    Lane lane[kMaxLanes];
     std::string err;
 };
 
 namespace {
 
+std::mutex g_err_mutex;   // lanes of one helm_solve may report errors concurrently
+
 helm_status fail(helm_hierarchy *H, helm_status st, const std::string &msg) {
-    if (H)
+    if (H) {
+        std::lock_guard<std::mutex> lock(g_err_mutex);
         H->err = msg;
-    else
+    } else {
         g_thread_error = msg;
+    }
     return st;
 }
 
@@ -122,35 +141,40 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     Hp->btab_f = c.take<float>(12 * (size_t)K);
     Hp->atab_d = c.take<double>(20 * (size_t)K);
     Hp->btab_d = c.take<double>(12 * (size_t)K);
-    for (int j = 0; j <= o.m_out; ++j) Hp->Vout[j] = vec(0);
-    for (int j = 0; j < o.m_out; ++j) Hp->Zout[j] = vec(0);
-    for (int j = 0; j <= o.m_h; ++j) Hp->Vs[j] = vec(0);
-    for (int j = 0; j < o.m_h; ++j) Hp->Zs[j] = vec(0);
-    Hp->x64 = c.take<c64>(g[0].nn);
-    Hp->b64 = c.take<c64>(g[0].nn);
-    for (int j = 0; j <= o.m_2h; ++j) Hp->V2[j] = vec(1);
-    for (int j = 0; j < o.m_2h; ++j) Hp->Z2[j] = vec(1);
-    Hp->e2 = vec(1);
-    Hp->r2 = vec(1);
-    Hp->vy = vec(1);
-    Hp->vr = vec(1);
-    for (int j = 0; j <= o.m_4h; ++j) Hp->P4[j] = vec(2);
-    for (int j = 0; j < o.m_4h; ++j) Hp->Z4[j] = vec(2);
-    Hp->e4 = vec(2);
-    for (int l = 0; l < 3; ++l) Hp->tmp[l] = vec(l);
-    for (int l = 0; l < 2; ++l)
-        Hp->wrest[l] = c.take<char>(es * (size_t)(g[l].n[2] / 2 + 1) * (g[l].n[1] + 1) * (g[l].n[0] / 2 + 1));
-    Hp->st_outer = c.take<KState>(1);
-    Hp->st_smooth = c.take<KState>(1);
-    Hp->st_k2h = c.take<KState>(1);
-    Hp->st_bottom = c.take<KState>(1);
-    Hp->st_hook = c.take<KState>(1);
-    size_t np = (size_t)kRedBlocks * 2 * 48;
-    for (int l = 0; l < 3; ++l)
-        np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2], kTzCandidates[0]));
-    Hp->rb.partials = c.take<double>(np);
-    Hp->rb.counter = c.take<unsigned>(64);
-    Hp->dscratch = c.take<double>(256);
+    const int nl = (o.lanes > 1) ? o.lanes : 1;
+    if (H) H->nlanes = nl;
+    for (int li = 0; li < nl; ++li) {
+        Lane &Ln = Hp->lane[li];
+        for (int j = 0; j <= o.m_out; ++j) Ln.Vout[j] = vec(0);
+        for (int j = 0; j < o.m_out; ++j) Ln.Zout[j] = vec(0);
+        for (int j = 0; j <= o.m_h; ++j) Ln.Vs[j] = vec(0);
+        for (int j = 0; j < o.m_h; ++j) Ln.Zs[j] = vec(0);
+        Ln.x64 = c.take<c64>(g[0].nn);
+        Ln.b64 = c.take<c64>(g[0].nn);
+        for (int j = 0; j <= o.m_2h; ++j) Ln.V2[j] = vec(1);
+        for (int j = 0; j < o.m_2h; ++j) Ln.Z2[j] = vec(1);
+        Ln.e2 = vec(1);
+        Ln.r2 = vec(1);
+        Ln.vy = vec(1);
+        Ln.vr = vec(1);
+        for (int j = 0; j <= o.m_4h; ++j) Ln.P4[j] = vec(2);
+        for (int j = 0; j < o.m_4h; ++j) Ln.Z4[j] = vec(2);
+        Ln.e4 = vec(2);
+        for (int l = 0; l < 3; ++l) Ln.tmp[l] = vec(l);
+        for (int l = 0; l < 2; ++l)
+            Ln.wrest[l] = c.take<char>(es * (size_t)(g[l].n[2] / 2 + 1) * (g[l].n[1] + 1) * (g[l].n[0] / 2 + 1));
+        Ln.st_outer = c.take<KState>(1);
+        Ln.st_smooth = c.take<KState>(1);
+        Ln.st_k2h = c.take<KState>(1);
+        Ln.st_bottom = c.take<KState>(1);
+        Ln.st_hook = c.take<KState>(1);
+        size_t np = (size_t)kRedBlocks * 2 * 48;
+        for (int l = 0; l < 3; ++l)
+            np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2], kTzCandidates[0]));
+        Ln.rb.partials = c.take<double>(np);
+        Ln.rb.counter = c.take<unsigned>(64);
+        Ln.dscratch = c.take<double>(256);
+    }
     return c.off + 256;
 }
 
@@ -253,9 +277,10 @@ template <typename T>
 struct Eng {
     using R = decltype(T{}.re);
     helm_hierarchy *H;
+    Lane *Ln;
     hipStream_t s;
 
-    explicit Eng(helm_hierarchy *h) : H(h), s(h->s) {}
+    explicit Eng(helm_hierarchy *h, int lane = 0) : H(h), Ln(&h->lane[lane]), s(h->lane[lane].s) {}
 
     const LevelArgs<R> &L(int l) const;
     long long nn(int l) const { return H->geom[l].nn; }
@@ -264,20 +289,20 @@ struct Eng {
     hipError_t stencil(int l, int mode, bool shifted, double wJ, const void *x, const void *g, const void *base,
                        void *y, bool norm = false, KState *st = nullptr) {
         StencilCall c{mode, shifted ? 1 : 0, wJ, x, g, base, y, norm, EPI_NORM_INIT, st, 0};
-        return launch_stencil<R, T, T, T>(L(l), c, H->rb, s);
+        return launch_stencil<R, T, T, T>(L(l), c, Ln->rb, s);
     }
 
     // coarse = R (g - op x) from level l to l+1 (eq. full-weighting fused with the residual)
     hipError_t resid_restrict(int l, bool shifted, const T *x, const T *g, T *coarse) {
-        HIP_CHK(stencil(l, M_RESID_R, shifted, 0.0, x, g, nullptr, H->wrest[l]));
-        return launch_restrict_y<T>(H->geom[l], H->geom[l + 1], static_cast<const T *>(H->wrest[l]), coarse, s);
+        HIP_CHK(stencil(l, M_RESID_R, shifted, 0.0, x, g, nullptr, Ln->wrest[l]));
+        return launch_restrict_y<T>(H->geom[l], H->geom[l + 1], static_cast<const T *>(Ln->wrest[l]), coarse, s);
     }
 
     // y = J_nJ(op, g; w) from zero; tmp is a scratch vector of the level
     hipError_t jacobi(int l, bool shifted, int nJ, double w, const T *g, T *y) {
         if (nJ == 1) return launch_jac1<R, T>(L(l), shifted, w, g, y, s);
         HIP_CHK(stencil(l, M_JAC2, shifted, w, nullptr, g, nullptr, y));
-        T *a = y, *b = v(H->tmp[l]);
+        T *a = y, *b = v(Ln->tmp[l]);
         for (int it = 2; it < nJ; ++it) {
             HIP_CHK(stencil(l, M_JSWEEP, shifted, w, a, g, nullptr, b));
             std::swap(a, b);
@@ -294,8 +319,8 @@ struct Eng {
     // neither written nor normalised.
     hipError_t arnoldi(int l, T **V, int k, KState *st, bool last) {
         HIP_CHK(launch_dots<T>((const T *const *)V, k + 1, V[k + 1], true, nn(l), EPI_ARNOLDI_SEL, st, k, nullptr,
-                               H->rb, s));
-        HIP_CHK(launch_axpy_dots<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, H->rb, s, !last));
+                               Ln->rb, s));
+        HIP_CHK(launch_axpy_dots<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, Ln->rb, s, !last));
         if (!last) HIP_CHK(launch_axpy_scale<T>((const T *const *)V, k + 1, V[k + 1], nn(l), st, s));
         return hipSuccess;
     }
@@ -310,7 +335,7 @@ struct Eng {
         for (int cyc = 0; cyc < cycles; ++cyc) {
             const bool from_zero = (cyc == 0 && x0_zero);
             if (from_zero)
-                HIP_CHK(launch_dots<T>(nullptr, 0, g, true, nn(l), EPI_NORM_INIT, st, 0, nullptr, H->rb, s));
+                HIP_CHK(launch_dots<T>(nullptr, 0, g, true, nn(l), EPI_NORM_INIT, st, 0, nullptr, Ln->rb, s));
             else
                 HIP_CHK(stencil(l, M_RESID, shifted, 0.0, x, g, nullptr, V[0], true, st));
             HIP_CHK(launch_scale<T>(from_zero ? g : V[0], V[0], nn(l), st, s));
@@ -332,21 +357,21 @@ struct Eng {
         const int m = H->opt.m_4h;
         T *P[kM4Max + 1], *Zb[kM4Max];
         P[0] = const_cast<T *>(q);
-        for (int j = 1; j <= m; ++j) P[j] = v(H->P4[j]);
-        for (int j = 0; j < m; ++j) Zb[j] = v(H->Z4[j]);
+        for (int j = 1; j <= m; ++j) P[j] = v(Ln->P4[j]);
+        for (int j = 0; j < m; ++j) Zb[j] = v(Ln->Z4[j]);
         for (int j = 0; j < m; ++j) {
             HIP_CHK(jacobi(2, true, H->opt.nJ_4h, H->opt.omega_4h, P[j], Zb[j]));
             HIP_CHK(stencil(2, M_APPLY, true, 0.0, Zb[j], nullptr, nullptr, P[j + 1]));
         }
-        HIP_CHK(launch_gram<T>((const T *const *)P, m + 1, nn(2), H->st_bottom, H->rb, s));
-        HIP_CHK((launch_combine<T, T>(e, (const T *const *)Zb, m, nn(2), H->st_bottom, false, true, s)));
+        HIP_CHK(launch_gram<T>((const T *const *)P, m + 1, nn(2), Ln->st_bottom, Ln->rb, s));
+        HIP_CHK((launch_combine<T, T>(e, (const T *const *)Zb, m, nn(2), Ln->st_bottom, false, true, s)));
         return hipSuccess;
     }
 
     // V^sigma_2h(q), eq. shifted-auxiliary-cycle
     hipError_t vcycle(const T *q, T *out) {
         const helm_options &o = H->opt;
-        T *y = v(H->vy), *r = v(H->vr), *q4 = v(H->P4[0]), *e4 = v(H->e4);
+        T *y = v(Ln->vy), *r = v(Ln->vr), *q4 = v(Ln->P4[0]), *e4 = v(Ln->e4);
         HIP_CHK(jacobi(1, true, o.nJ_2h, o.omega_2h, q, y));                 // y = J(B_2h, q)
         HIP_CHK(resid_restrict(1, true, y, q, q4));                          // q_4h = R(q - B y)
         HIP_CHK(bottom(q4, e4));                                             // e_4h = C_4h(q_4h)
@@ -364,7 +389,7 @@ struct Eng {
     // K_2h(r), eq. unshifted-middle-solve
     hipError_t k2h(const T *r, T *e) {
         auto prec = [this](const T *in, T *out) { return vcycle(in, out); };
-        return gmres(1, false, prec, r, e, true, H->opt.m_2h, H->opt.c_2h, H->st_k2h, H->V2, H->Z2);
+        return gmres(1, false, prec, r, e, true, H->opt.m_2h, H->opt.c_2h, Ln->st_k2h, Ln->V2, Ln->Z2);
     }
 
     // S_h(g; x0) -> x (in place when x0 == x)
@@ -372,12 +397,12 @@ struct Eng {
         auto prec = [this](const T *in, T *out) {
             return jacobi(0, false, H->opt.nJ_h, H->opt.omega_h, in, out);
         };
-        return gmres(0, false, prec, g, x, x0_zero, H->opt.m_h, 1, H->st_smooth, H->Vs, H->Zs);
+        return gmres(0, false, prec, g, x, x0_zero, H->opt.m_h, 1, Ln->st_smooth, Ln->Vs, Ln->Zs);
     }
 
     // Algorithm 1: z = M_h^{-1} r
     hipError_t precond(const T *r, T *z) {
-        T *r2 = v(H->r2), *e2 = v(H->e2);
+        T *r2 = v(Ln->r2), *e2 = v(Ln->e2);
         HIP_CHK(smooth(r, z, true));                                          // 1: z_pre = S_h(r; 0)
         HIP_CHK(resid_restrict(0, false, z, r, r2));                         // 2: r_2h = R(r - A z_pre)
         HIP_CHK(k2h(r2, e2));                                                 // 3: e_2h = K_2h(r_2h)
@@ -387,7 +412,7 @@ struct Eng {
     }
 
     hipError_t read_state(const KState *st) {
-        HIP_CHK(hipMemcpyAsync(H->host_state, st, sizeof(KState), hipMemcpyDeviceToHost, s));
+        HIP_CHK(hipMemcpyAsync(Ln->host_state, st, sizeof(KState), hipMemcpyDeviceToHost, s));
         return hipStreamSynchronize(s);
     }
 
@@ -396,33 +421,33 @@ struct Eng {
         const helm_options &o = H->opt;
         const long long n = nn(0);
         T *V[kMMax + 1], *Zp[kMMax];
-        for (int j = 0; j <= o.m_out; ++j) V[j] = v(H->Vout[j]);
-        for (int j = 0; j < o.m_out; ++j) Zp[j] = v(H->Zout[j]);
-        KState *st = H->st_outer;
+        for (int j = 0; j <= o.m_out; ++j) V[j] = v(Ln->Vout[j]);
+        for (int j = 0; j < o.m_out; ++j) Zp[j] = v(Ln->Zout[j]);
+        KState *st = Ln->st_outer;
         const int max_outer = o.max_outer > 0 ? o.max_outer : 1000;
-        HIP_TRY((launch_qapply<double, T, c64>(H->Ld[0], f, H->b64, s)));   // b = Q_h f
-        HIP_TRY(launch_dots<c64>(nullptr, 0, H->b64, true, n, EPI_STORE, nullptr, 0, H->dscratch, H->rb, s));
-        HIP_TRY(hipMemcpyAsync(H->host_scratch, H->dscratch, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY((launch_qapply<double, T, c64>(H->Ld[0], f, Ln->b64, s)));   // b = Q_h f
+        HIP_TRY(launch_dots<c64>(nullptr, 0, Ln->b64, true, n, EPI_STORE, nullptr, 0, Ln->dscratch, Ln->rb, s));
+        HIP_TRY(hipMemcpyAsync(Ln->host_scratch, Ln->dscratch, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const double bn = std::sqrt(H->host_scratch[0]);
-        HIP_TRY(launch_fill_zero<c64>(H->x64, n, s));
+        const double bn = std::sqrt(Ln->host_scratch[0]);
+        HIP_TRY(launch_fill_zero<c64>(Ln->x64, n, s));
         int its = 0;
         double rel = 0.0;
         helm_status status = HELM_OK;
         if (!(bn == bn) || bn > 1e300) return fail(H, HELM_BREAKDOWN, "non-finite right-hand side");
         if (bn == 0.0) {
-            HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], H->x64, u, s)));
+            HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], Ln->x64, u, s)));
             *iters = 0;
             *relres = 0.0;
             return HELM_OK;
         }
         for (;;) {
             // true residual in FP64 arithmetic: r = b - A_h x
-            StencilCall c{M_RESID, 0, 0.0, H->x64, H->b64, nullptr, V[0], true, EPI_NORM_INIT, st, 0};
-            HIP_TRY((launch_stencil<double, c64, c64, T>(H->Ld[0], c, H->rb, s)));
+            StencilCall c{M_RESID, 0, 0.0, Ln->x64, Ln->b64, nullptr, V[0], true, EPI_NORM_INIT, st, 0};
+            HIP_TRY((launch_stencil<double, c64, c64, T>(H->Ld[0], c, Ln->rb, s)));
             HIP_TRY(read_state(st));
-            if (H->host_state->nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite residual");
-            rel = H->host_state->beta / bn;
+            if (Ln->host_state->nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite residual");
+            rel = Ln->host_state->beta / bn;
             if (rel <= tol) break;
             if (its >= max_outer) {
                 status = HELM_NOT_CONVERGED;
@@ -437,14 +462,14 @@ struct Eng {
                 HIP_TRY(arnoldi(0, V, k, st, k == o.m_out - 1));
                 HIP_TRY(read_state(st));
                 kk = k + 1;
-                const KState &hs = *H->host_state;
+                const KState &hs = *Ln->host_state;
                 if (hs.nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite Krylov quantity");
                 const double est = std::hypot(hs.g[k + 1][0], hs.g[k + 1][1]) / bn;
                 if (est <= tol || hs.breakdown || its >= max_outer) break;
             }
-            HIP_TRY((launch_combine<c64, T>(H->x64, (const T *const *)Zp, kk, n, st, true, false, s)));
+            HIP_TRY((launch_combine<c64, T>(Ln->x64, (const T *const *)Zp, kk, n, st, true, false, s)));
         }
-        HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], H->x64, u, s)));   // u = Q_h v
+        HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], Ln->x64, u, s)));   // u = Q_h v
         HIP_TRY(hipStreamSynchronize(s));
         *iters = its;
         *relres = rel;
@@ -456,6 +481,22 @@ template <>
 const LevelArgs<float> &Eng<c32>::L(int l) const { return H->Lf[l]; }
 template <>
 const LevelArgs<double> &Eng<c64>::L(int l) const { return H->Ld[l]; }
+
+// pinned host buffers and the streams helm_setup created for lanes 1..
+void release_lanes(helm_hierarchy *H) {
+    for (int li = 0; li < kMaxLanes; ++li) {
+        Lane &Ln = H->lane[li];
+        if (Ln.host_state) (void)hipHostFree(Ln.host_state);
+        if (Ln.host_scratch) (void)hipHostFree(Ln.host_scratch);
+        if (Ln.own_stream) {
+            (void)hipStreamSynchronize(Ln.s);
+            (void)hipStreamDestroy(Ln.s);
+        }
+        Ln.host_state = nullptr;
+        Ln.host_scratch = nullptr;
+        Ln.own_stream = false;
+    }
+}
 
 helm_status check_options(const helm_options *o, std::string &msg) {
     if (!o) { msg = "options pointer is NULL"; return HELM_EINVAL; }
@@ -478,6 +519,7 @@ helm_status check_options(const helm_options *o, std::string &msg) {
     for (int tz : kTzCandidates) tz_ok = tz_ok || o->tile_tz == tz;
     if (!tz_ok) { msg = "tile_tz must be 0, 2, 4, 8, 16, 32 or 64"; return HELM_EINVAL; }
     if (!in(o->tile_split, -1, 1)) { msg = "tile_split must be -1, 0 or 1"; return HELM_EINVAL; }
+    if (!in(o->lanes, 0, kMaxLanes)) { msg = "lanes must be in 0..8"; return HELM_EINVAL; }
     return HELM_OK;
 }
 
@@ -514,8 +556,8 @@ bool level_ok(int l) { return l >= 0 && l <= 2; }
 template <typename T>
 hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     Eng<T> E(H);
-    T *x = static_cast<T *>(H->tmp[l]);
-    T *y = static_cast<T *>(l == 0 ? H->Vs[0] : (l == 1 ? H->vy : H->e4));
+    T *x = static_cast<T *>(H->lane[0].tmp[l]);
+    T *y = static_cast<T *>(l == 0 ? H->lane[0].Vs[0] : (l == 1 ? H->lane[0].vy : H->lane[0].e4));
     HIP_CHK(launch_fill_zero<T>(x, E.nn(l), H->s));
     hipEvent_t a, b;
     HIP_CHK(hipEventCreate(&a));
@@ -605,6 +647,7 @@ helm_status helm_default_options(helm_options *o) {
     o->stream = nullptr;
     o->tile_tz = 0;
     o->tile_split = -1;
+    o->lanes = 1;
     return HELM_OK;
 }
 
@@ -653,26 +696,34 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
 
     auto bail = [&](helm_status code, const std::string &m) {
         g_thread_error = m;
-        if (H->host_state) (void)hipHostFree(H->host_state);
-        if (H->host_scratch) (void)hipHostFree(H->host_scratch);
+        release_lanes(H);
         delete H;
         return code;
     };
     hipError_t e;
-    if ((e = hipHostMalloc((void **)&H->host_state, sizeof(KState))) != hipSuccess ||
-        (e = hipHostMalloc((void **)&H->host_scratch, 64 * sizeof(double))) != hipSuccess)
-        return bail(HELM_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     hipStream_t s = H->s;
-    // counters start at zero
-    if ((e = hipMemsetAsync(H->rb.counter, 0, 64 * sizeof(unsigned), s)) != hipSuccess)
-        return bail(HELM_EHIP, hipGetErrorString(e));
+    for (int li = 0; li < H->nlanes; ++li) {
+        Lane &Ln = H->lane[li];
+        Ln.s = s;
+        if (li > 0) {
+            if ((e = hipStreamCreateWithFlags(&Ln.s, hipStreamNonBlocking)) != hipSuccess)
+                return bail(HELM_EHIP, std::string("lane stream: ") + hipGetErrorString(e));
+            Ln.own_stream = true;
+        }
+        if ((e = hipHostMalloc((void **)&Ln.host_state, sizeof(KState))) != hipSuccess ||
+            (e = hipHostMalloc((void **)&Ln.host_scratch, 64 * sizeof(double))) != hipSuccess)
+            return bail(HELM_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        // reduction counters start at zero
+        if ((e = hipMemsetAsync(Ln.rb.counter, 0, 64 * sizeof(unsigned), s)) != hipSuccess)
+            return bail(HELM_EHIP, hipGetErrorString(e));
+    }
     // velocity must be finite and positive
     const long long nphys = (long long)(nx + 1) * (ny + 1) * (nz + 1);
-    if ((e = launch_velocity_check(velocity, nphys, H->rb, H->dscratch, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(H->host_scratch, H->dscratch, 3 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+    if ((e = launch_velocity_check(velocity, nphys, H->lane[0].rb, H->lane[0].dscratch, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(H->lane[0].host_scratch, H->lane[0].dscratch, 3 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return bail(HELM_EHIP, std::string("velocity check: ") + hipGetErrorString(e));
-    if (H->host_scratch[2] != 0.0 || !(H->host_scratch[0] > 0.0))
+    if (H->lane[0].host_scratch[2] != 0.0 || !(H->lane[0].host_scratch[0] > 0.0))
         return bail(HELM_EINVAL, "velocity must be finite and positive everywhere");
 
     const double Lpml = n_pml * h;
@@ -724,13 +775,59 @@ helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, v
     if (f == u) return fail(H, HELM_EINVAL, "f and u must not alias");
     const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
     const long long n = H->geom[0].nn;
-    helm_status worst = HELM_OK;
-    for (int r = 0; r < nrhs; ++r) {
+    auto one = [&](int lane, int r) {
         const char *fr = static_cast<const char *>(f) + (size_t)r * n * es;
         char *ur = static_cast<char *>(u) + (size_t)r * n * es;
-        helm_status st = (H->prec == HELM_FP64)
-                             ? Eng<c64>(H).solve_one((const c64 *)fr, (c64 *)ur, tol, iters + r, relres + r)
-                             : Eng<c32>(H).solve_one((const c32 *)fr, (c32 *)ur, tol, iters + r, relres + r);
+        return (H->prec == HELM_FP64)
+                   ? Eng<c64>(H, lane).solve_one((const c64 *)fr, (c64 *)ur, tol, iters + r, relres + r)
+                   : Eng<c32>(H, lane).solve_one((const c32 *)fr, (c32 *)ur, tol, iters + r, relres + r);
+    };
+    const int L = std::min(H->nlanes, nrhs);
+    if (L <= 1) {
+        helm_status worst = HELM_OK;
+        for (int r = 0; r < nrhs; ++r) {
+            helm_status st = one(0, r);
+            if (st < 0) return st;
+            if (st == HELM_NOT_CONVERGED) worst = st;
+        }
+        return worst;
+    }
+    // Lanes 1.. start after the work already queued on the caller's stream (lane 0);
+    // each lane takes the next right-hand side until none is left.  Every solve
+    // ends by synchronising its lane's stream, so all results are in place on return.
+    hipEvent_t ready;
+    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ready, H->s);
+    for (int li = 1; li < L && e == hipSuccess; ++li) e = hipStreamWaitEvent(H->lane[li].s, ready, 0);
+    int dev = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        return fail(H, HELM_EHIP, std::string("lane start: ") + hipGetErrorString(e));
+    }
+    std::atomic<int> next(0);
+    std::vector<helm_status> lane_st(L, HELM_OK);
+    std::vector<std::thread> pool;
+    for (int li = 0; li < L; ++li)
+        pool.emplace_back([&, li] {
+            if (li > 0 && hipSetDevice(dev) != hipSuccess) {
+                lane_st[li] = fail(H, HELM_EHIP, "lane thread could not select the device");
+                return;
+            }
+            for (int r = next++; r < nrhs; r = next++) {
+                helm_status st = one(li, r);
+                if (st < 0) {
+                    lane_st[li] = st;
+                    next = nrhs;   // stop handing out work
+                    return;
+                }
+                if (st == HELM_NOT_CONVERGED) lane_st[li] = st;
+            }
+        });
+    for (auto &t : pool) t.join();
+    (void)hipEventDestroy(ready);
+    helm_status worst = HELM_OK;
+    for (helm_status st : lane_st) {
         if (st < 0) return st;
         if (st == HELM_NOT_CONVERGED) worst = st;
     }
@@ -743,8 +840,7 @@ helm_status helm_grad(helm_hierarchy *H, const void *, int, double, float *) {
 
 void helm_destroy(helm_hierarchy *H) {
     if (!H) return;
-    if (H->host_state) (void)hipHostFree(H->host_state);
-    if (H->host_scratch) (void)hipHostFree(H->host_scratch);
+    release_lanes(H);
     delete H;
 }
 
@@ -872,12 +968,12 @@ helm_status helm_vec_dots(helm_hierarchy *H, int level, int k, const void *const
     helm_status st = dispatch(H, [&](auto E) {
         using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
         return launch_dots<TT>((const TT *const *)V, k, (const TT *)w, true, E.nn(level), EPI_STORE, nullptr, 0,
-                               H->dscratch, H->rb, E.s);
+                               H->lane[0].dscratch, H->lane[0].rb, E.s);
     });
     if (st != HELM_OK) return st;
-    HIP_TRY(hipMemcpyAsync(H->host_scratch, H->dscratch, 2 * (k + 1) * sizeof(double), hipMemcpyDeviceToHost, H->s));
+    HIP_TRY(hipMemcpyAsync(H->lane[0].host_scratch, H->lane[0].dscratch, 2 * (k + 1) * sizeof(double), hipMemcpyDeviceToHost, H->s));
     HIP_TRY(hipStreamSynchronize(H->s));
-    std::memcpy(out, H->host_scratch, 2 * (k + 1) * sizeof(double));
+    std::memcpy(out, H->lane[0].host_scratch, 2 * (k + 1) * sizeof(double));
     return HELM_OK;
 }
 
@@ -885,23 +981,23 @@ helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const v
     if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
     if (!level_ok(level) || k < 1 || k > kMMax || !V || !w || !out)
         return fail(H, HELM_EINVAL, "invalid orthonormalize arguments");
-    HIP_TRY(hipMemsetAsync(H->st_hook, 0, sizeof(KState), H->s));
+    HIP_TRY(hipMemsetAsync(H->lane[0].st_hook, 0, sizeof(KState), H->s));
     helm_status st = dispatch(H, [&](auto E) -> hipError_t {
         using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
         const TT *const *VV = (const TT *const *)V;
-        HIP_CHK(launch_dots<TT>(VV, k, (const TT *)w, false, E.nn(level), EPI_ARNOLDI1, H->st_hook, 0, nullptr, H->rb,
+        HIP_CHK(launch_dots<TT>(VV, k, (const TT *)w, false, E.nn(level), EPI_ARNOLDI1, H->lane[0].st_hook, 0, nullptr, H->lane[0].rb,
                                 E.s));
-        HIP_CHK(launch_axpy_dots<TT>(VV, k, (TT *)w, E.nn(level), H->st_hook, H->rb, E.s));
-        return launch_axpy_scale<TT>(VV, k, (TT *)w, E.nn(level), H->st_hook, E.s);
+        HIP_CHK(launch_axpy_dots<TT>(VV, k, (TT *)w, E.nn(level), H->lane[0].st_hook, H->lane[0].rb, E.s));
+        return launch_axpy_scale<TT>(VV, k, (TT *)w, E.nn(level), H->lane[0].st_hook, E.s);
     });
     if (st != HELM_OK) return st;
-    HIP_TRY(hipMemcpyAsync(H->host_state, H->st_hook, sizeof(KState), hipMemcpyDeviceToHost, H->s));
+    HIP_TRY(hipMemcpyAsync(H->lane[0].host_state, H->lane[0].st_hook, sizeof(KState), hipMemcpyDeviceToHost, H->s));
     HIP_TRY(hipStreamSynchronize(H->s));
     for (int j = 0; j < k; ++j) {
-        out[2 * j] = H->host_state->h1[j][0] + H->host_state->h2[j][0];
-        out[2 * j + 1] = H->host_state->h1[j][1] + H->host_state->h2[j][1];
+        out[2 * j] = H->lane[0].host_state->h1[j][0] + H->lane[0].host_state->h2[j][0];
+        out[2 * j + 1] = H->lane[0].host_state->h1[j][1] + H->lane[0].host_state->h2[j][1];
     }
-    out[2 * k] = H->host_state->hk1;
+    out[2 * k] = H->lane[0].host_state->hk1;
     out[2 * k + 1] = 0.0;
     return HELM_OK;
 }

@@ -77,6 +77,12 @@ def test_bad_dims_rejected(L, dims, n_pml):
     assert L.helm_last_error(None)
 
 
+def test_workspace_grows_by_one_solver_copy_per_lane(L):
+    sizes = [_ws(L, (56, 56, 56), 4, _opts(lanes=k))[1] for k in (1, 2, 3)]
+    assert sizes[1] > sizes[0] and sizes[2] - sizes[1] == sizes[1] - sizes[0]
+    assert _ws(L, (56, 56, 56), 4, _opts(lanes=0))[1] == sizes[0]
+
+
 def test_good_tile_options_accepted(L):
     for tz in (0, 2, 4, 8, 16, 32, 64):
         for split in (-1, 0, 1):
@@ -86,7 +92,8 @@ def test_good_tile_options_accepted(L):
 
 @pytest.mark.parametrize("field,value", [("m_out", 0), ("m_2h", 13), ("m_4h", 9), ("nJ_h", 0), ("c_2h", 0),
                                          ("iofd_K", 0), ("omega_2h", -0.1), ("struct_size", 8), ("precision", 7),
-                                         ("tile_tz", 3), ("tile_tz", 128), ("tile_split", 2), ("tile_split", -2)])
+                                         ("tile_tz", 3), ("tile_tz", 128), ("tile_split", 2), ("tile_split", -2),
+                                         ("lanes", 9), ("lanes", -1)])
 def test_bad_options_rejected(L, field, value):
     rc, _ = _ws(L, (24, 24, 24), 4, _opts(**{field: value}))
     assert rc == -1

@@ -290,6 +290,29 @@ def test_solve_fixed_tiling_fp32(tiling):
     assert err <= 2e-5, (err, its, its_o)
 
 
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_solve_lanes_match_one_lane(lanes):
+    """Right-hand sides solved concurrently on several lanes give exactly the
+    single-lane results (deterministic reductions, no shared state)."""
+    from paper_2608_22946_amd import helm
+    n, npml = 44, 10
+    vel = grf_velocity(n, n, n, seed=31, corr_len=8.0)
+    omega = omega_for_ppw(float(vel.min()), H)
+    N = n + 2 * npml
+    f = np.stack([point_source((N, N, N), (N // 2 + 5 * i, N // 2 - 3 * i, N // 2 + 2 * i), H, dtype=np.complex64)
+                  for i in range(3)])
+    fd = torch.from_numpy(f).cuda()
+    kw = dict(precision="fp32", table=load_iofd_table(), device="cuda:0", tile_tz=8, tile_split=0)
+    one = helm.Hierarchy(torch.from_numpy(vel), H, omega, npml, lanes=1, **kw)
+    many = helm.Hierarchy(torch.from_numpy(vel), H, omega, npml, lanes=lanes, **kw)
+    u1, it1, rel1, rc1 = one.solve(fd, 1e-6)
+    u2, it2, rel2, rc2 = many.solve(fd, 1e-6)
+    torch.cuda.synchronize()
+    assert rc1 == 0 and rc2 == 0
+    assert list(it1) == list(it2) and np.array_equal(rel1, rel2)
+    assert torch.equal(u1, u2)
+
+
 def test_solve_dense_direct_fp64():
     """16^3 total grid: GPU solve to 1e-10 against a dense direct solve."""
     vel = grf_velocity(8, 8, 8, seed=6, corr_len=3.0)
