@@ -549,8 +549,8 @@ bool level_ok(int l) { return l >= 0 && l <= 2; }
 // Pick, per level and kernel family, the number of z planes each stencil
 // wavefront marches through and whether the stencils run as one launch or as
 // interior + border launches: time the family's kernel (an operator apply, or a
-// fused two-sweep Jacobi) with HIP events on the caller's stream, best of two
-// trials, for every candidate and keep the fastest.  Long marches amortise the
+// fused two-sweep Jacobi; six launches) with HIP events on the caller's stream,
+// best of two trials, for every candidate and keep the fastest.  Long marches amortise the
 // plane pipeline; short ones give small grids enough workgroups; the split
 // costs a second launch but lets interior tiles run at higher occupancy.
 template <typename T>
@@ -572,6 +572,7 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     for (int cand = 0; cand < 2 * (int)(sizeof(kTzCandidates) / sizeof(int)) && err == hipSuccess; ++cand) {
         const int tz = kTzCandidates[cand / 2], split = cand % 2;
         if (tz > H->geom[l].n[2] + 1 && tz != kTzCandidates[0] && H->opt.tile_tz == 0) break;
+        if (tz == 2 && H->geom[l].nn > (1LL << 20) && H->opt.tile_tz == 0) continue;   // never the fastest there
         if ((H->opt.tile_tz != 0 && tz != H->opt.tile_tz) || (H->opt.tile_split >= 0 && split != H->opt.tile_split))
             continue;
         H->Lf[l].tz[fam] = H->Ld[l].tz[fam] = tz;
@@ -580,7 +581,7 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
         float ms = 1e30f;
         for (int trial = 0; trial < 2 && err == hipSuccess; ++trial) {
             if ((err = hipEventRecord(a, H->s)) != hipSuccess) break;
-            for (int r = 0; r < 3 && err == hipSuccess; ++r) err = run();
+            for (int r = 0; r < 6 && err == hipSuccess; ++r) err = run();
             if (err != hipSuccess || (err = hipEventRecord(b, H->s)) != hipSuccess) break;
             if ((err = hipEventSynchronize(b)) != hipSuccess) break;
             float t = 0.f;
