@@ -198,6 +198,25 @@ def test_random_table_apply_and_q():
     assert rel(to_np(p.g.apply(0, 2, p.dev(x))), p.o.apply(0, 2, x)) <= 1e-13
 
 
+@pytest.mark.parametrize("phys,npml", [((4, 4, 504), 2), ((1020, 4, 4), 2), ((8, 60, 8), 0)],
+                         ids=["tall-z", "long-x", "narrow-no-pml"])
+def test_extreme_aspect_grids(phys, npml):
+    """Degenerate shapes: 2h / 4h levels only one or two intervals wide, long
+    z marches, many x tiles with the edge strips, no PML."""
+    vel = grf_velocity(*phys, seed=17, corr_len=3.0)
+    p = Pair(vel, npml, "fp64")
+    for level in (0, 1, 2):
+        for op in (0, 1):
+            x = p.rand(level, 500 + 2 * level + op)
+            assert rel(to_np(p.g.apply(level, op, p.dev(x))), p.o.apply(level, op, x)) <= 1e-12, (level, op)
+        g = p.rand(level, 510 + level)
+        assert rel(to_np(p.g.jacobi(level, 1, p.dev(g), 2, 0.8)), p.o.jacobi(level, 1, g, 2, 0.8)) <= 1e-12
+    for level in (0, 1):
+        g, x = p.rand(level, 520 + level), p.rand(level, 530 + level)
+        c = to_np(p.g.residual_restrict(level, 1, p.dev(g), p.dev(x)))
+        assert rel(c, p.o.restrict(level, p.o.residual(level, 1, g, x))) <= 1e-12
+
+
 def test_no_pml_box():
     """n_pml = 0: all interior rows take the shell form."""
     p = Pair(homogeneous(64, 32, 24, 1700.0), 0, "fp64")
@@ -384,6 +403,18 @@ def test_c2_residual_restrict(c2):
         c = p.g.residual_restrict(level, op, p.dev(g), p.dev(x)).cpu().numpy().astype(np.complex128)
         ref = p.o.restrict(level, p.o.residual(level, op, g.astype(np.complex128), x.astype(np.complex128)))
         assert rel(c, ref) <= 1e-6
+
+
+def test_c2_jacobi(c2):
+    """Fused two-sweep Jacobi at the full size on every level (A_h with omega_h; B_2h, B_4h as in the
+    V-cycle and the bottom solver), every node against the checker."""
+    p, _ = c2
+    rng = np.random.default_rng(7)
+    for level, op, w in [(0, 0, 0.8), (1, 1, 0.8), (2, 1, 0.2)]:
+        shp = p.g.shape(level)
+        g = (rng.standard_normal(shp, dtype=np.float32) + 1j * rng.standard_normal(shp, dtype=np.float32))
+        y = p.g.jacobi(level, op, p.dev(g), 2, w).cpu().numpy().astype(np.complex128)
+        assert rel(y, p.o.jacobi(level, op, g.astype(np.complex128), 2, w)) <= 1e-6, level
 
 
 def test_c2_solve_residual(c2):
