@@ -152,7 +152,7 @@ hipError_t launch_scale(const T *x, T *y, long long n, const KState *st, hipStre
 // x (+)= sum_j y_j Z_j with y from the state: back substitution of the
 // rotated Hessenberg (from_backsolve) or the stored s-step coefficients.
 template <typename TX, typename TZ>
-hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, const KState *st, bool from_backsolve,
+hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, KState *st, bool from_backsolve,
                           bool overwrite, hipStream_t s);
 
 template <typename T>

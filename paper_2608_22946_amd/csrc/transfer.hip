@@ -66,47 +66,72 @@ __global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__r
     c[(long long)Zc * C.sy + (long long)Y * C.sx + X] = o;
 }
 
-// one thread per fine node: fine += P coarse.  Along each axis a fine node
-// 2j takes coarse node j with weight 1 and a fine node 2j+1 takes j and j+1
-// with weight 1/2 each; coarse boundary nodes contribute zero.
+// fine += P coarse, one thread per coarse cell (X, Y, Z), X in [0, nc): it
+// updates the fine nodes 2X + i, 2Y + j, 2Z + k (i, j, k in {0, 1}) from the
+// eight coarse nodes X + a, Y + b, Z + c (a, b, c in {0, 1}).  Along each axis
+// a fine node 2X takes coarse X with weight 1 and a fine node 2X + 1 takes X
+// and X + 1 with weight 1/2 each; coarse boundary nodes contribute zero and
+// fine boundary nodes are left unchanged.  Each coarse value is loaded once per
+// cell instead of once per fine node, and the two x-neighbouring fine nodes of
+// a cell are adjacent in memory.
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__restrict__ c, T *__restrict__ f) {
-    const int x = blockIdx.x * kTX + threadIdx.x, y = blockIdx.y * kTY + threadIdx.y, z = blockIdx.z;
-    if (x < 1 || x > F.n[0] - 1 || y < 1 || y > F.n[1] - 1 || z < 1 || z > F.n[2] - 1) return;
-    const int xa = x >> 1, xb = (x + 1) >> 1, ya = y >> 1, yb = (y + 1) >> 1, za = z >> 1, zb = (z + 1) >> 1;
-    const real_of<T> hx = (x & 1) ? (real_of<T>)0.5 : (real_of<T>)1, hy = (y & 1) ? (real_of<T>)0.5 : (real_of<T>)1,
-                     hz = (z & 1) ? (real_of<T>)0.5 : (real_of<T>)1;
-    real_of<T> sr = 0, si = 0;
+    using R = real_of<T>;
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Z = blockIdx.z;
+    if (X >= C.n[0] || Y >= C.n[1]) return;
+    // coarse corner values, zero outside the coarse interior
+    R cr[2][2][2], ci[2][2][2];
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz) {
-        const int Zc = cz ? zb : za;
-        if ((cz && zb == za) || Zc < 1 || Zc > C.n[2] - 1) continue;
+    for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 2; ++cy) {
-            const int Yc = cy ? yb : ya;
-            if ((cy && yb == ya) || Yc < 1 || Yc > C.n[1] - 1) continue;
-            const T *row = c + (long long)Zc * C.sy + (long long)Yc * C.sx;
-            real_of<T> rr = 0, ri = 0;
-            if (xa >= 1 && xa <= C.n[0] - 1) {
-                const T v = row[xa];
-                rr += v.re;
-                ri += v.im;
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int Xc = X + cx, Yc = Y + cy, Zc = Z + cz;
+                const bool in = Xc >= 1 && Xc <= C.n[0] - 1 && Yc >= 1 && Yc <= C.n[1] - 1 && Zc >= 1 &&
+                                Zc <= C.n[2] - 1;
+                T v;
+                v.re = 0;
+                v.im = 0;
+                if (in) v = c[(long long)Zc * C.sy + (long long)Yc * C.sx + Xc];
+                cr[cz][cy][cx] = v.re;
+                ci[cz][cy][cx] = v.im;
             }
-            if (xb != xa && xb >= 1 && xb <= C.n[0] - 1) {
-                const T v = row[xb];
-                rr += v.re;
-                ri += v.im;
+    const R half = (R)0.5;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int z = 2 * Z + k;
+        if (z < 1) continue;   // z <= 2 (nc - 1) + 1 = F.n[2] - 1 always
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int y = 2 * Y + j;
+            if (y < 1) continue;
+            // the four coarse values of this fine row, weighted along z and y
+            R pr[2], pi[2];
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                R zr[2], zi[2];
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy) {
+                    zr[cy] = k ? half * (cr[0][cy][cx] + cr[1][cy][cx]) : cr[0][cy][cx];
+                    zi[cy] = k ? half * (ci[0][cy][cx] + ci[1][cy][cx]) : ci[0][cy][cx];
+                }
+                pr[cx] = j ? half * (zr[0] + zr[1]) : zr[0];
+                pi[cx] = j ? half * (zi[0] + zi[1]) : zi[0];
             }
-            sr += rr;
-            si += ri;
+            T *row = f + (long long)z * F.sy + (long long)y * F.sx + 2 * X;
+            if (X >= 1) {   // fine node 2X (x = 0 is a boundary node)
+                T o = row[0];
+                o.re += pr[0];
+                o.im += pi[0];
+                row[0] = o;
+            }
+            T o = row[1];   // fine node 2X + 1
+            o.re += half * (pr[0] + pr[1]);
+            o.im += half * (pi[0] + pi[1]);
+            row[1] = o;
         }
     }
-    const real_of<T> w = hx * hy * hz;
-    const long long i = (long long)z * F.sy + (long long)y * F.sx + x;
-    T o = f[i];
-    o.re += w * sr;
-    o.im += w * si;
-    f[i] = o;
 }
 
 }  // namespace
@@ -114,6 +139,10 @@ __global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__
 namespace {
 dim3 node_grid(const Geom &g) {
     return dim3((unsigned)((g.n[0] + kTX) / kTX), (unsigned)((g.n[1] + kTY) / kTY), (unsigned)(g.n[2] + 1));
+}
+// one thread per cell of g: n[0] x n[1] x n[2]
+dim3 cell_grid(const Geom &g) {
+    return dim3((unsigned)((g.n[0] + kTX - 1) / kTX), (unsigned)((g.n[1] + kTY - 1) / kTY), (unsigned)g.n[2]);
 }
 }  // namespace
 
@@ -131,7 +160,9 @@ hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, T
 
 template <typename T>
 hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, T *f, hipStream_t s) {
-    hipLaunchKernelGGL((k_prolong_add<T>), node_grid(fine), dim3(kTX, kTY), 0, s, coarse, fine, c, f);
+    if (fine.n[0] != 2 * coarse.n[0] || fine.n[1] != 2 * coarse.n[1] || fine.n[2] != 2 * coarse.n[2])
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_prolong_add<T>), cell_grid(coarse), dim3(kTX, kTY), 0, s, coarse, fine, c, f);
     return hipGetLastError();
 }
 

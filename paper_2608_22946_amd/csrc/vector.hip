@@ -34,6 +34,13 @@ __device__ __forceinline__ D2 cdot(T a, T b) {   // conj(a) * b
 
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
 
+// Elementwise kernels run one thread per element over a full grid: measured on
+// fine-level vectors this streams faster than any grid-stride loop, with or
+// without several elements in flight per thread, because the blocks then sweep
+// memory in order.  Reductions keep a grid-stride loop over a fixed number of
+// blocks (one element per step: unrolled steps measured slower).
+__device__ __forceinline__ long long elem_index() { return blockIdx.x * (long long)blockDim.x + threadIdx.x; }
+
 // Block-reduce NS complex sums, store them as this block's partials, then
 // return true in the last block to arrive (which may read every block's partials).
 constexpr int kRedThreads = 1024;      // threads per reduction block (16 wavefronts)
@@ -105,14 +112,12 @@ __device__ void state_init(KState *st, double beta) {
     st->g[0][0] = beta;
 }
 
-// Column k of the Hessenberg matrix: h (k+1 entries) and h_{k+1,k}; apply the
-// previous rotations, build the one annihilating h_{k+1,k}, rotate g.
-__device__ void givens_column(KState *st, int k, const D2 *h, double hk1) {
-    double cr[kMMax + 1][2];
-    for (int j = 0; j <= k; ++j) {
-        cr[j][0] = h[j].r;
-        cr[j][1] = h[j].i;
-    }
+// Column k of the Hessenberg matrix: cr (k+1 entries, rotated in place) and
+// h_{k+1,k}; apply the previous rotations, build the one annihilating h_{k+1,k},
+// rotate g.  One thread runs it; cr lives in LDS so that the loops with a
+// run-time bound need no private (scratch) array and add nothing to the
+// register budget of the streaming loop that precedes the epilogue.
+__device__ void givens_column(KState *st, int k, double (*cr)[2], double hk1) {
     for (int j = 0; j < k; ++j) {
         const double c = st->cs[j], sr = st->sn[j][0], si = st->sn[j][1];
         const double ar = cr[j][0], ai = cr[j][1], br = cr[j + 1][0], bi = cr[j + 1][1];
@@ -173,8 +178,7 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
     D2 acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = {0, 0};
-#pragma unroll 2
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = elem_index(); i < n; i += (long long)gridDim.x * blockDim.x) {
         const T wi = w[i];
 #pragma unroll
         for (int j = 0; j < NV; ++j) acc[j] = acc[j] + cdot(P.v[j][i], wi);
@@ -199,10 +203,11 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
             // Kahan-Parlett "twice is enough": if the first projection keeps at
             // least half of ||w||^2, w - V h1 is orthogonal to working accuracy
             // and the second pass is skipped.
+            __shared__ double col[kMMax + 1][2];
             double c2 = 0.0;
             for (int j = 0; j < NV; ++j) {
-                st->h1[j][0] = tot[j].r;
-                st->h1[j][1] = tot[j].i;
+                st->h1[j][0] = col[j][0] = tot[j].r;
+                st->h1[j][1] = col[j][1] = tot[j].i;
                 c2 += tot[j].r * tot[j].r + tot[j].i * tot[j].i;
             }
             const double w2 = tot[NS - 1].r, r2 = w2 - c2;
@@ -212,7 +217,7 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
                     st->h2[j][1] = tot[j].i;
                 }
                 st->reorth = 0;
-                givens_column(st, NV - 1, tot, sqrt(r2));
+                givens_column(st, NV - 1, col, sqrt(r2));
             } else {
                 st->reorth = 1;
             }
@@ -245,9 +250,7 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
     D2 acc[NV + 1];
 #pragma unroll
     for (int s = 0; s <= NV; ++s) acc[s] = {0, 0};
-    // two elements per iteration in flight while the registers allow it
-#pragma unroll (NV <= 6 ? 2 : 1)
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = elem_index(); i < n; i += (long long)gridDim.x * blockDim.x) {
         T v[NV];
         T wi = w[i];
 #pragma unroll
@@ -265,17 +268,18 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
     __shared__ D2 tot[kSlots];
     sum_partials<NV + 1>(rb, tot);
     if (threadIdx.x == 0) {
-        D2 h[NV];
+        __shared__ double col[kMMax + 1][2];
         double c2 = 0.0;
         for (int j = 0; j < NV; ++j) {
             st->h2[j][0] = tot[j].r;
             st->h2[j][1] = tot[j].i;
-            h[j] = {st->h1[j][0] + tot[j].r, st->h1[j][1] + tot[j].i};
+            col[j][0] = st->h1[j][0] + tot[j].r;
+            col[j][1] = st->h1[j][1] + tot[j].i;
             c2 += tot[j].r * tot[j].r + tot[j].i * tot[j].i;
         }
         // ||w - V h2||^2 = ||w||^2 - ||h2||^2 for orthonormal V
         const double hk1 = sqrt(fmax(tot[NV].r - c2, 0.0));
-        givens_column(st, NV - 1, h, hk1);
+        givens_column(st, NV - 1, col, hk1);
         reset_ticket(rb.counter);
     }
 }
@@ -297,64 +301,65 @@ __global__ void __launch_bounds__(256) k_axpy_scale(Ptrs<T, NV> P, T *__restrict
         hi[j] = (real_of<T>)hs[j][1];
     }
     const real_of<T> sc = (real_of<T>)hs[NV][0];
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        T wi = w[i];
+    const long long i = elem_index();
+    if (i >= n) return;
+    T wi = w[i];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const T v = P.v[j][i];
-            wi.re -= hr[j] * v.re - hi[j] * v.im;
-            wi.im -= hr[j] * v.im + hi[j] * v.re;
-        }
-        wi.re *= sc;
-        wi.im *= sc;
-        w[i] = wi;
+    for (int j = 0; j < NV; ++j) {
+        const T v = P.v[j][i];
+        wi.re -= hr[j] * v.re - hi[j] * v.im;
+        wi.im -= hr[j] * v.im + hi[j] * v.re;
     }
+    wi.re *= sc;
+    wi.im *= sc;
+    w[i] = wi;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_scale(const T *__restrict__ x, T *__restrict__ y, long long n,
                                               const KState *st) {
     const real_of<T> sc = (real_of<T>)st->scale;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        T v = x[i];
-        v.re *= sc;
-        v.im *= sc;
-        y[i] = v;
+    const long long i = elem_index();
+    if (i >= n) return;
+    T v = x[i];
+    v.re *= sc;
+    v.im *= sc;
+    y[i] = v;
+}
+
+// y = R^{-1} g: back substitution of the rotated Hessenberg over its kk columns
+// (guarded zero pivots), y_j = 0 beyond; one thread.
+__global__ void __launch_bounds__(64) k_backsolve(KState *st, int nv) {
+    if (threadIdx.x != 0) return;
+    const int kk = st->kk < nv ? st->kk : nv;
+    for (int j = kk; j < kMMax; ++j) st->y[j][0] = st->y[j][1] = 0.0;
+    for (int i = kk - 1; i >= 0; --i) {
+        double sr = st->g[i][0], si = st->g[i][1];
+        for (int j = i + 1; j < kk; ++j) {
+            const double hr = st->H[i][j][0], hi = st->H[i][j][1];
+            sr -= hr * st->y[j][0] - hi * st->y[j][1];
+            si -= hr * st->y[j][1] + hi * st->y[j][0];
+        }
+        const double dr = st->H[i][i][0], di = st->H[i][i][1];
+        const double d2 = dr * dr + di * di;
+        if (d2 == 0.0) {
+            st->y[i][0] = st->y[i][1] = 0.0;
+        } else {
+            st->y[i][0] = (sr * dr + si * di) / d2;
+            st->y[i][1] = (si * dr - sr * di) / d2;
+        }
     }
 }
 
-// x (+)= sum_j y_j Z_j, y by back substitution R y = g (guarded zero pivots) or
-// taken from st->y
+// x (+)= sum_j y_j Z_j with y from st->y (written by k_backsolve or by the
+// s-step Gram solve)
 template <typename TX, typename TZ, int NV>
 __global__ void __launch_bounds__(256) k_combine(TX *__restrict__ x, Ptrs<TZ, NV> Zp, long long n, const KState *st,
-                                                int from_backsolve, int overwrite) {
+                                                int overwrite) {
     __shared__ double ys[NV][2];
-    if (threadIdx.x == 0) {
-        if (from_backsolve) {
-            const int kk = st->kk < NV ? st->kk : NV;
-            for (int j = kk; j < NV; ++j) ys[j][0] = ys[j][1] = 0.0;
-            for (int i = kk - 1; i >= 0; --i) {
-                double sr = st->g[i][0], si = st->g[i][1];
-                for (int j = i + 1; j < kk; ++j) {
-                    const double hr = st->H[i][j][0], hi = st->H[i][j][1];
-                    sr -= hr * ys[j][0] - hi * ys[j][1];
-                    si -= hr * ys[j][1] + hi * ys[j][0];
-                }
-                const double dr = st->H[i][i][0], di = st->H[i][i][1];
-                const double d2 = dr * dr + di * di;
-                if (d2 == 0.0) {
-                    ys[i][0] = ys[i][1] = 0.0;
-                } else {
-                    ys[i][0] = (sr * dr + si * di) / d2;
-                    ys[i][1] = (si * dr - sr * di) / d2;
-                }
-            }
-        } else {
-            for (int j = 0; j < NV; ++j) {
-                ys[j][0] = st->y[j][0];
-                ys[j][1] = st->y[j][1];
-            }
-        }
+    if (threadIdx.x < NV) {
+        ys[threadIdx.x][0] = st->y[threadIdx.x][0];
+        ys[threadIdx.x][1] = st->y[threadIdx.x][1];
     }
     __syncthreads();
     real_of<TX> yr[NV], yi[NV];
@@ -363,23 +368,23 @@ __global__ void __launch_bounds__(256) k_combine(TX *__restrict__ x, Ptrs<TZ, NV
         yr[j] = (real_of<TX>)ys[j][0];
         yi[j] = (real_of<TX>)ys[j][1];
     }
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        TX acc;
-        if (overwrite) {
-            acc.re = 0;
-            acc.im = 0;
-        } else {
-            acc = x[i];
-        }
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const TZ z = Zp.v[j][i];
-            const real_of<TX> zr = (real_of<TX>)z.re, zi = (real_of<TX>)z.im;
-            acc.re += yr[j] * zr - yi[j] * zi;
-            acc.im += yr[j] * zi + yi[j] * zr;
-        }
-        x[i] = acc;
+    const long long i = elem_index();
+    if (i >= n) return;
+    TX acc;
+    if (overwrite) {
+        acc.re = 0;
+        acc.im = 0;
+    } else {
+        acc = x[i];
     }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const TZ z = Zp.v[j][i];
+        const real_of<TX> zr = (real_of<TX>)z.re, zi = (real_of<TX>)z.im;
+        acc.re += yr[j] * zr - yi[j] * zi;
+        acc.im += yr[j] * zi + yi[j] * zr;
+    }
+    x[i] = acc;
 }
 
 // Gram matrix G_ij = <P_i, P_j> (i <= j) of the s-step basis P_0..P_{NP-1}, then
@@ -391,8 +396,7 @@ __global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KStat
     D2 acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = {0, 0};
-#pragma unroll 2
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = elem_index(); i < n; i += (long long)gridDim.x * blockDim.x) {
         T v[NP];
 #pragma unroll
         for (int a = 0; a < NP; ++a) v[a] = P.v[a][i];
@@ -470,33 +474,33 @@ __global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KStat
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill_zero(T *x, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        T z;
-        z.re = 0;
-        z.im = 0;
-        x[i] = z;
-    }
+    const long long i = elem_index();
+    if (i >= n) return;
+    T z;
+    z.re = 0;
+    z.im = 0;
+    x[i] = z;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_add(const T *__restrict__ x, T *__restrict__ y, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        T v = y[i];
-        const T a = x[i];
-        v.re += a.re;
-        v.im += a.im;
-        y[i] = v;
-    }
+    const long long i = elem_index();
+    if (i >= n) return;
+    T v = y[i];
+    const T a = x[i];
+    v.re += a.re;
+    v.im += a.im;
+    y[i] = v;
 }
 
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) k_convert(const TI *__restrict__ x, TO *__restrict__ y, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        TO o;
-        o.re = (real_of<TO>)x[i].re;
-        o.im = (real_of<TO>)x[i].im;
-        y[i] = o;
-    }
+    const long long i = elem_index();
+    if (i >= n) return;
+    TO o;
+    o.re = (real_of<TO>)x[i].re;
+    o.im = (real_of<TO>)x[i].im;
+    y[i] = o;
 }
 
 // velocity on the nodes of one level: nearest physical value in the PML
@@ -577,11 +581,11 @@ int red_blocks(long long n) {
     return (int)b;
 }
 
-int stream_blocks(long long n) {
-    long long b = (n + 1023) / 1024;
+// blocks of an elementwise kernel: one thread per element, 256 per block
+unsigned stream_blocks(long long n) {
+    long long b = (n + 255) / 256;
     if (b < 1) b = 1;
-    if (b > 8192) b = 8192;
-    return (int)b;
+    return (unsigned)b;
 }
 
 template <typename T, int NV>
@@ -658,7 +662,7 @@ hipError_t launch_axpy_dots(const T *const *V, int nv, T *w, long long n, KState
 
 template <typename T>
 hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KState *st, hipStream_t s) {
-    const int nb = stream_blocks(n);
+    const unsigned nb = stream_blocks(n);
 #define HELM_AS(NV) \
     case NV: hipLaunchKernelGGL((k_axpy_scale<T, NV>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, n, st); break;
     switch (nv) {
@@ -678,13 +682,19 @@ hipError_t launch_scale(const T *x, T *y, long long n, const KState *st, hipStre
 }
 
 template <typename TX, typename TZ>
-hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, const KState *st, bool from_backsolve,
+hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, KState *st, bool from_backsolve,
                           bool overwrite, hipStream_t s) {
-    const int nb = stream_blocks(n);
+    if (nz < 1 || nz > kMMax) return hipErrorInvalidValue;
+    if (from_backsolve) {
+        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, st, nz);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const unsigned nb = stream_blocks(n);
 #define HELM_CB(NV)                                                                                            \
     case NV:                                                                                                   \
         hipLaunchKernelGGL((k_combine<TX, TZ, NV>), dim3(nb), dim3(256), 0, s, x, pack<TZ, NV>(Z), n, st,       \
-                           (int)from_backsolve, (int)overwrite);                                               \
+                           (int)overwrite);                                                                    \
         break;
     switch (nz) {
         HELM_CB(1) HELM_CB(2) HELM_CB(3) HELM_CB(4) HELM_CB(5) HELM_CB(6) HELM_CB(7) HELM_CB(8) HELM_CB(9)
@@ -753,11 +763,11 @@ hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, 
 HELM_INST(c32)
 HELM_INST(c64)
 #undef HELM_INST
-template hipError_t launch_combine<c32, c32>(c32 *, const c32 *const *, int, long long, const KState *, bool, bool,
+template hipError_t launch_combine<c32, c32>(c32 *, const c32 *const *, int, long long, KState *, bool, bool,
                                              hipStream_t);
-template hipError_t launch_combine<c64, c64>(c64 *, const c64 *const *, int, long long, const KState *, bool, bool,
+template hipError_t launch_combine<c64, c64>(c64 *, const c64 *const *, int, long long, KState *, bool, bool,
                                              hipStream_t);
-template hipError_t launch_combine<c64, c32>(c64 *, const c32 *const *, int, long long, const KState *, bool, bool,
+template hipError_t launch_combine<c64, c32>(c64 *, const c32 *const *, int, long long, KState *, bool, bool,
                                              hipStream_t);
 template hipError_t launch_convert<c32, c64>(const c32 *, c64 *, long long, hipStream_t);
 template hipError_t launch_convert<c64, c32>(const c64 *, c32 *, long long, hipStream_t);
