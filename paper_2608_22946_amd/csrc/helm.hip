@@ -312,9 +312,9 @@ struct Eng {
     }
 
     // Arnoldi step: V[k+1] <- A Z[k] orthonormalised against V[0..k] (CGS2), Givens update of column k
-    // Classical Gram-Schmidt with a second pass only where the first one lost
-    // more than half of ||w||^2 (decided on the device: the second-pass kernel
-    // returns at once otherwise).  The last step of a cycle (last = true) stops
+    // Classical Gram-Schmidt with a second pass only where the first one left
+    // less than kReorthEta of ||w||^2 (decided on the device: the second-pass
+    // kernel returns at once otherwise).  The last step of a cycle (last = true) stops
     // after the Hessenberg column: the next basis vector is never used, so it is
     // neither written nor normalised.
     hipError_t arnoldi(int l, T **V, int k, KState *st, bool last) {
@@ -333,12 +333,18 @@ struct Eng {
         for (int j = 0; j <= m; ++j) V[j] = v(Vv[j]);
         for (int j = 0; j < m; ++j) Zp[j] = v(Zv[j]);
         for (int cyc = 0; cyc < cycles; ++cyc) {
+            // The first basis vector is the residual itself, unnormalised (the
+            // state keeps its 1/beta for the projections): g from zero, else
+            // g - op x.  Its preconditioned image is then beta times larger, so
+            // Hessenberg column 0 and y_0 carry the factor and x = Z y is unchanged.
             const bool from_zero = (cyc == 0 && x0_zero);
-            if (from_zero)
+            if (from_zero) {
+                V[0] = const_cast<T *>(g);   // read only
                 HIP_CHK(launch_dots<T>(nullptr, 0, g, true, nn(l), EPI_NORM_INIT, st, 0, nullptr, Ln->rb, s));
-            else
+            } else {
+                V[0] = v(Vv[0]);
                 HIP_CHK(stencil(l, M_RESID, shifted, 0.0, x, g, nullptr, V[0], true, st));
-            HIP_CHK(launch_scale<T>(from_zero ? g : V[0], V[0], nn(l), st, s));
+            }
             for (int k = 0; k < m; ++k) {
                 HIP_CHK(prec(V[k], Zp[k]));
                 HIP_CHK(stencil(l, M_APPLY, shifted, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
@@ -453,8 +459,7 @@ struct Eng {
                 status = HELM_NOT_CONVERGED;
                 break;
             }
-            HIP_TRY(launch_scale<T>(V[0], V[0], n, st, s));
-            int kk = 0;
+            int kk = 0;   // V[0] = r stays unnormalised (the state holds 1/beta)
             for (int k = 0; k < o.m_out; ++k) {
                 HIP_TRY(precond(V[k], Zp[k]));
                 ++its;
@@ -983,6 +988,8 @@ helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const v
     if (!level_ok(level) || k < 1 || k > kMMax || !V || !w || !out)
         return fail(H, HELM_EINVAL, "invalid orthonormalize arguments");
     HIP_TRY(hipMemsetAsync(H->lane[0].st_hook, 0, sizeof(KState), H->s));
+    static const double one = 1.0;   // the caller's V_0 is normalised
+    HIP_TRY(hipMemcpyAsync(&H->lane[0].st_hook->vs0, &one, sizeof(double), hipMemcpyHostToDevice, H->s));
     helm_status st = dispatch(H, [&](auto E) -> hipError_t {
         using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
         const TT *const *VV = (const TT *const *)V;

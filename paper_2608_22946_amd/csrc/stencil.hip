@@ -304,6 +304,7 @@ __device__ void norm_epilogue(const RedBuf &rb, int nblocks, KState *st) {
         double beta = sqrt(red[0]);
         st->beta = beta;
         st->scale = (beta > 0.0) ? 1.0 / beta : 0.0;
+        st->vs0 = st->scale;
         st->kk = 0;
         st->breakdown = 0;
         st->nonfinite = !(beta == beta && beta < 1e300);

@@ -105,6 +105,7 @@ __device__ void sum_partials(const RedBuf &rb, D2 *out) {
 __device__ void state_init(KState *st, double beta) {
     st->beta = beta;
     st->scale = (beta > 0.0) ? 1.0 / beta : 0.0;
+    st->vs0 = st->scale;   // the residual itself stays the stored first basis vector
     st->kk = 0;
     st->breakdown = 0;
     st->nonfinite = !(beta == beta && beta < 1e300);
@@ -156,7 +157,8 @@ __device__ void givens_column(KState *st, int k, double (*cr)[2], double hk1) {
     st->g[k][1] = c * gi;
     st->kk = k + 1;
     st->hk1 = hk1;
-    const bool ok = hk1 > kBreakdown * st->beta;
+    // column 0 was built from the unnormalised first vector (scaled by 1/vs0)
+    const bool ok = (k == 0 ? hk1 * st->vs0 : hk1) > kBreakdown * st->beta;
     st->scale = ok ? 1.0 / hk1 : 0.0;
     if (!ok) st->breakdown = 1;
     if (!(hk1 == hk1) || !(st->g[k + 1][0] == st->g[k + 1][0])) st->nonfinite = 1;
@@ -194,16 +196,18 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
                 out[2 * s + 1] = tot[s].i;
             }
         } else if (EPI == EPI_ARNOLDI1) {
+            if (NV > 0) tot[0] = {tot[0].r * st->vs0, tot[0].i * st->vs0};   // onto the normalised V_0
             for (int j = 0; j < NV; ++j) {
                 st->h1[j][0] = tot[j].r;
                 st->h1[j][1] = tot[j].i;
             }
             st->reorth = 1;
         } else if (EPI == EPI_ARNOLDI_SEL && NV > 0) {
-            // Kahan-Parlett "twice is enough": if the first projection keeps at
-            // least half of ||w||^2, w - V h1 is orthogonal to working accuracy
-            // and the second pass is skipped.
+            // selective second pass: if the first projection keeps at least
+            // kReorthEta of ||w||^2, w - V h1 is orthogonal to a few units of
+            // roundoff and the second pass is skipped.
             __shared__ double col[kMMax + 1][2];
+            tot[0] = {tot[0].r * st->vs0, tot[0].i * st->vs0};   // onto the normalised V_0
             double c2 = 0.0;
             for (int j = 0; j < NV; ++j) {
                 st->h1[j][0] = col[j][0] = tot[j].r;
@@ -211,7 +215,7 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
                 c2 += tot[j].r * tot[j].r + tot[j].i * tot[j].i;
             }
             const double w2 = tot[NS - 1].r, r2 = w2 - c2;
-            if (r2 >= 0.5 * w2) {
+            if (r2 >= kReorthEta * w2) {
                 for (int j = 0; j < NV; ++j) {
                     st->h2[j][0] = tot[j].r;
                     st->h2[j][1] = tot[j].i;
@@ -236,9 +240,10 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
                                                   RedBuf rb) {
     if (!st->reorth) return;   // the first pass was enough (the whole grid returns; no ticket is taken)
     __shared__ double hs[NV][2];
-    if (threadIdx.x < NV) {
-        hs[threadIdx.x][0] = st->h1[threadIdx.x][0];
-        hs[threadIdx.x][1] = st->h1[threadIdx.x][1];
+    if (threadIdx.x < NV) {   // coefficients of the stored vectors (V_0 is stored unnormalised)
+        const double f = threadIdx.x == 0 ? st->vs0 : 1.0;
+        hs[threadIdx.x][0] = st->h1[threadIdx.x][0] * f;
+        hs[threadIdx.x][1] = st->h1[threadIdx.x][1] * f;
     }
     __syncthreads();
     real_of<T> hr[NV], hi[NV];
@@ -269,6 +274,7 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
     sum_partials<NV + 1>(rb, tot);
     if (threadIdx.x == 0) {
         __shared__ double col[kMMax + 1][2];
+        tot[0] = {tot[0].r * st->vs0, tot[0].i * st->vs0};   // onto the normalised V_0
         double c2 = 0.0;
         for (int j = 0; j < NV; ++j) {
             st->h2[j][0] = tot[j].r;
@@ -288,9 +294,10 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
 template <typename T, int NV>
 __global__ void __launch_bounds__(256) k_axpy_scale(Ptrs<T, NV> P, T *__restrict__ w, long long n, const KState *st) {
     __shared__ double hs[NV + 1][2];
-    if (threadIdx.x < NV) {
-        hs[threadIdx.x][0] = st->h2[threadIdx.x][0];
-        hs[threadIdx.x][1] = st->h2[threadIdx.x][1];
+    if (threadIdx.x < NV) {   // coefficients of the stored vectors (V_0 is stored unnormalised)
+        const double f = threadIdx.x == 0 ? st->vs0 : 1.0;
+        hs[threadIdx.x][0] = st->h2[threadIdx.x][0] * f;
+        hs[threadIdx.x][1] = st->h2[threadIdx.x][1] * f;
     }
     if (threadIdx.x == 0) hs[NV][0] = st->scale;
     __syncthreads();
@@ -313,18 +320,6 @@ __global__ void __launch_bounds__(256) k_axpy_scale(Ptrs<T, NV> P, T *__restrict
     wi.re *= sc;
     wi.im *= sc;
     w[i] = wi;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_scale(const T *__restrict__ x, T *__restrict__ y, long long n,
-                                              const KState *st) {
-    const real_of<T> sc = (real_of<T>)st->scale;
-    const long long i = elem_index();
-    if (i >= n) return;
-    T v = x[i];
-    v.re *= sc;
-    v.im *= sc;
-    y[i] = v;
 }
 
 // y = R^{-1} g: back substitution of the rotated Hessenberg over its kk columns
@@ -675,12 +670,6 @@ hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KStat
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_scale(const T *x, T *y, long long n, const KState *st, hipStream_t s) {
-    hipLaunchKernelGGL((k_scale<T>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n, st);
-    return hipGetLastError();
-}
-
 template <typename TX, typename TZ>
 hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, KState *st, bool from_backsolve,
                           bool overwrite, hipStream_t s) {
@@ -756,7 +745,6 @@ hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, 
     template hipError_t launch_axpy_dots<T>(const T *const *, int, T *, long long, KState *, const RedBuf &,      \
                                             hipStream_t, bool);                                                   \
     template hipError_t launch_axpy_scale<T>(const T *const *, int, T *, long long, KState *, hipStream_t);       \
-    template hipError_t launch_scale<T>(const T *, T *, long long, const KState *, hipStream_t);                  \
     template hipError_t launch_gram<T>(const T *const *, int, long long, KState *, const RedBuf &, hipStream_t); \
     template hipError_t launch_fill_zero<T>(T *, long long, hipStream_t);                                      \
     template hipError_t launch_add<T>(const T *, T *, long long, hipStream_t);
