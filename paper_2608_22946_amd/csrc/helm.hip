@@ -398,12 +398,35 @@ struct Eng {
         return gmres(1, false, prec, r, e, true, H->opt.m_2h, H->opt.c_2h, Ln->st_k2h, Ln->V2, Ln->Z2);
     }
 
-    // S_h(g; x0) -> x (in place when x0 == x)
+    // S_h(g; x0) -> x (in place when x0 == x): one GMRES(m_h) cycle right-preconditioned by J_nJh(A_h).
+    // For m_h <= kSstepMax the minimal-residual iterate over the same Krylov space is
+    // computed from the s-step basis P_0 = r_0, P_{j+1} = A_h J(P_j) and the FP64 Gram
+    // matrix (as in the bottom solver): two vector passes per step fewer than Arnoldi's
+    // projections, with a basis of at most three vectors, well conditioned in FP64 even
+    // where A_h J is close to the identity.  Longer cycles use Arnoldi.
     hipError_t smooth(const T *g, T *x, bool x0_zero) {
-        auto prec = [this](const T *in, T *out) {
-            return jacobi(0, false, H->opt.nJ_h, H->opt.omega_h, in, out);
-        };
-        return gmres(0, false, prec, g, x, x0_zero, H->opt.m_h, 1, Ln->st_smooth, Ln->Vs, Ln->Zs);
+        const int m = H->opt.m_h;
+        if (m > kSstepMax) {
+            auto prec = [this](const T *in, T *out) {
+                return jacobi(0, false, H->opt.nJ_h, H->opt.omega_h, in, out);
+            };
+            return gmres(0, false, prec, g, x, x0_zero, m, 1, Ln->st_smooth, Ln->Vs, Ln->Zs);
+        }
+        T *P[kSstepMax + 1], *Zp[kSstepMax];
+        for (int j = 1; j <= m; ++j) P[j] = v(Ln->Vs[j]);
+        for (int j = 0; j < m; ++j) Zp[j] = v(Ln->Zs[j]);
+        if (x0_zero) {
+            P[0] = const_cast<T *>(g);   // read only
+        } else {
+            P[0] = v(Ln->Vs[0]);
+            HIP_CHK(stencil(0, M_RESID, false, 0.0, x, g, nullptr, P[0]));   // r_0 = g - A_h x_0
+        }
+        for (int j = 0; j < m; ++j) {
+            HIP_CHK(jacobi(0, false, H->opt.nJ_h, H->opt.omega_h, P[j], Zp[j]));
+            HIP_CHK(stencil(0, M_APPLY, false, 0.0, Zp[j], nullptr, nullptr, P[j + 1]));
+        }
+        HIP_CHK(launch_gram<T>((const T *const *)P, m + 1, nn(0), Ln->st_smooth, Ln->rb, s));
+        return launch_combine<T, T>(x, (const T *const *)Zp, m, nn(0), Ln->st_smooth, false, x0_zero, s);
     }
 
     // Algorithm 1: z = M_h^{-1} r

@@ -14,6 +14,7 @@ namespace helm {
 
 constexpr int kMMax = 12;       // longest Krylov restart supported (m_h, m_2h, m_out)
 constexpr int kM4Max = 8;       // longest bottom (s-step) basis
+constexpr int kSstepMax = 2;    // longest fine-level smoothing cycle computed with an s-step basis
 constexpr int kKMax = 128;      // most table intervals
 constexpr int kTileX = 62;      // output nodes per wavefront along x (64 lanes, 1-node halo each side)
 constexpr int kWavesY = 4;      // wavefronts (rows y) per workgroup

@@ -180,6 +180,21 @@ def test_smooth(pair, x0):
     assert err <= pair.tol(1e-10, 1e-4), err
 
 
+@pytest.mark.parametrize("m_h", [1, 3])
+@pytest.mark.parametrize("x0", [False, True])
+def test_smooth_cycle_lengths(m_h, x0):
+    """S_h with m_h = 1 takes the s-step (Gram) path, m_h = 3 the Arnoldi path; both
+    must give the checker's GMRES(m_h) iterate (FP64)."""
+    vel = grf_velocity(60, 20, 28, seed=14, corr_len=5.0)
+    p = Pair(vel, 4, "fp64", m_h=m_h)
+    g = p.rand(0, 214)
+    xi = p.rand(0, 215) if x0 else None
+    x = to_np(p.g.smooth(p.dev(g), p.dev(xi) if x0 else None))
+    ref = p.o.smooth(g.astype(complex), xi.astype(complex) if x0 else None)
+    err = rel(x, ref)
+    assert err <= 1e-10, err
+
+
 def test_precond(pair):
     r = pair.rand(0, 206)
     z = to_np(pair.g.precond(pair.dev(r)))
