@@ -54,6 +54,7 @@ typedef struct {
     or_level lev[3];
     double h, omega;
     int n_pml;
+    int nphys[3];        /* physical intervals per axis (the velocity grid) */
     const double *tab;   /* [node][function][value, slope] */
     int K;
     double eta_max;
@@ -326,6 +327,165 @@ static void level_residual(const or_hier *H, const or_level *L, int op, const cp
             for (int x = 0; x <= L->n[0]; ++x) {
                 size_t i = idx3(L->n, x, y, z);
                 r[i] = on_boundary(L->n, x, y, z) ? 0 : g[i] - r[i];
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* Transposes and derivatives with respect to m = 1/c^2 (adjoint-state  */
+/* gradient of a misfit of u = Q_h v, A_h v = Q_h f)                    */
+/* ------------------------------------------------------------------ */
+
+/* d alpha_f / d eta of the Hermite interpolant of hermite() */
+static double hermite_deta(const or_hier *H, int f, double eta)
+{
+    const double de = H->eta_max / H->K;
+    int k = (int)floor(eta / de);
+    if (k < 0) k = 0;
+    if (k > H->K - 1) k = H->K - 1;
+    double t = (eta - k * de) / de;
+    double p0 = H->tab[(k * 8 + f) * 2 + 0], m0 = H->tab[(k * 8 + f) * 2 + 1];
+    double p1 = H->tab[((k + 1) * 8 + f) * 2 + 0], m1 = H->tab[((k + 1) * 8 + f) * 2 + 1];
+    double d00 = 6 * t * t - 6 * t;           /* derivatives in t of the four basis cubics */
+    double d10 = 3 * t * t - 4 * t + 1;
+    double d01 = -6 * t * t + 6 * t;
+    double d11 = 3 * t * t - 2 * t;
+    return (d00 * p0 + d10 * de * m0 + d01 * p1 + d11 * de * m1) / de;
+}
+
+/* At a node with velocity c on spacing ell: kappa = omega ell / c = omega ell sqrt(m);
+ * eta = min(kappa / 2pi, 0.4).  d eta / d m = kappa c^2 / (4 pi) below the clamp, 0 on it;
+ * d kappa^2 / d m = kappa^2 c^2. */
+static double deta_dm(double c, double kappa)
+{
+    double eta = kappa / (2.0 * M_PI);
+    return eta >= 0.4 ? 0.0 : kappa * c * c / (4.0 * M_PI);
+}
+
+/* d/dm of the 27 row coefficients of row_stencil (mu = 1) at interior node (x,y,z), times ell^2:
+ * the transverse weights (a4, a5/4, (1-a4-a5)/4) and mass weights (a1, a2/6, a3/12,
+ * (1-a1-a2-a3)/8) differentiated through alpha(eta), and kappa^2 differentiated directly. */
+static void row_stencil_dm(const or_hier *H, const or_level *L, int x, int y, int z, cplx Kd[27])
+{
+    double c = L->c[idx3(L->n, x, y, z)];
+    double kappa, a[5], da[5];
+    row_coeffs(H, c, L->ell, &kappa, a);
+    double eta = kappa / (2.0 * M_PI);
+    if (eta > 0.4) eta = 0.4;
+    double de = deta_dm(c, kappa);
+    for (int f = 0; f < 5; ++f) da[f] = hermite_deta(H, f, eta) * de;
+    double k2 = kappa * kappa, dk2 = kappa * kappa * c * c;
+    double dT[3] = {da[3], da[4] / 4.0, -(da[3] + da[4]) / 4.0};
+    double Mw[4] = {a[0], a[1] / 6.0, a[2] / 12.0, (1.0 - a[0] - a[1] - a[2]) / 8.0};
+    double dMw[4] = {da[0], da[1] / 6.0, da[2] / 12.0, -(da[0] + da[1] + da[2]) / 8.0};
+    int pos[3] = {x, y, z};
+    cplx w[3][3];
+    for (int j = 0; j < 3; ++j) {
+        int i = pos[j];
+        cplx xn = L->xin[j][i], xp = L->xih[j][i], xm = L->xih[j][i - 1];
+        w[j][0] = -xn * xm;
+        w[j][1] = xn * (xp + xm);
+        w[j][2] = -xn * xp;
+    }
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int d[3] = {dx, dy, dz};
+                cplx k = 0;
+                for (int j = 0; j < 3; ++j) {
+                    int nz = 0;
+                    for (int q = 0; q < 3; ++q)
+                        if (q != j && d[q] != 0) ++nz;
+                    k += w[j][d[j] + 1] * dT[nz];
+                }
+                int shell = abs(dx) + abs(dy) + abs(dz);
+                k -= dk2 * Mw[shell] + k2 * dMw[shell];
+                Kd[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] = k;
+            }
+}
+
+/* shell weights of Q_h at a fine node (eq. q-operator) and their derivatives in m */
+static void q_weights(const or_hier *H, const or_level *L, int x, int y, int z, double Qm[4], double dQm[4])
+{
+    double c = L->c[idx3(L->n, x, y, z)];
+    double kappa = H->omega / c * L->ell;
+    double eta = kappa / (2.0 * M_PI);
+    if (eta > 0.4) eta = 0.4;
+    double b[3], db[3], de = deta_dm(c, kappa);
+    for (int f = 0; f < 3; ++f) {
+        b[f] = hermite(H, 5 + f, eta);
+        db[f] = hermite_deta(H, 5 + f, eta) * de;
+    }
+    Qm[0] = b[0];
+    Qm[1] = b[1] / 6.0;
+    Qm[2] = b[2] / 12.0;
+    Qm[3] = (1.0 - b[0] - b[1] - b[2]) / 8.0;
+    dQm[0] = db[0];
+    dQm[1] = db[1] / 6.0;
+    dQm[2] = db[2] / 12.0;
+    dQm[3] = -(db[0] + db[1] + db[2]) / 8.0;
+}
+
+/* y = op^T x on level L (op A or B on any level, Q on level 0): by definition of the
+ * transpose, every interior row i adds (row i, column j) * x_i to y_j for each interior
+ * neighbour j.  Serial, so the scatter has no races. */
+static void level_apply_t(const or_hier *H, const or_level *L, int op, const cplx *xv, cplx *yv)
+{
+    vzero(L->nn, yv);
+    for (int z = 1; z < L->n[2]; ++z)
+        for (int y = 1; y < L->n[1]; ++y)
+            for (int x = 1; x < L->n[0]; ++x) {
+                cplx xi = xv[idx3(L->n, x, y, z)];
+                cplx Kst[27];
+                double Qm[4], dQm[4];
+                if (op == OP_Q)
+                    q_weights(H, L, x, y, z, Qm, dQm);
+                else
+                    row_stencil(H, L, x, y, z, op_mu(H, op), Kst);
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            int xx = x + dx, yy = y + dy, zz = z + dz;
+                            if (on_boundary(L->n, xx, yy, zz)) continue;
+                            cplx coef = (op == OP_Q) ? Qm[abs(dx) + abs(dy) + abs(dz)]
+                                                     : Kst[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] /
+                                                           (L->ell * L->ell);
+                            yv[idx3(L->n, xx, yy, zz)] += coef * xi;
+                        }
+            }
+}
+
+/* y_i = (d_i op x)_i on level 0: row i of op differentiated with respect to m_i (the
+ * squared slowness at node i; every row depends on its own node only), op A or Q */
+static void level_apply_dm(const or_hier *H, int op, const cplx *xv, cplx *yv)
+{
+    const or_level *L = &H->lev[0];
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z <= L->n[2]; ++z)
+        for (int y = 0; y <= L->n[1]; ++y)
+            for (int x = 0; x <= L->n[0]; ++x) {
+                size_t i = idx3(L->n, x, y, z);
+                if (on_boundary(L->n, x, y, z)) {
+                    yv[i] = 0;
+                    continue;
+                }
+                cplx Kd[27];
+                double Qm[4], dQm[4];
+                if (op == OP_Q)
+                    q_weights(H, L, x, y, z, Qm, dQm);
+                else
+                    row_stencil_dm(H, L, x, y, z, Kd);
+                cplx s = 0;
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            int xx = x + dx, yy = y + dy, zz = z + dz;
+                            if (on_boundary(L->n, xx, yy, zz)) continue;
+                            cplx coef = (op == OP_Q) ? dQm[abs(dx) + abs(dy) + abs(dz)]
+                                                     : Kd[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] /
+                                                           (L->ell * L->ell);
+                            s += coef * xv[idx3(L->n, xx, yy, zz)];
+                        }
+                yv[i] = s;
             }
 }
 
@@ -655,6 +815,7 @@ int or_create(const float *vel_phys, int nx, int ny, int nz, double h, double om
     H->p.m_out = (int)params[12];
     for (int a = 0; a < 3; ++a) H->lev[0].n[a] = N[a];
     int nphys[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) H->nphys[a] = nphys[a];
     size_t nv = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
     double *vd = (double *)malloc(nv * sizeof(double));
     for (size_t i = 0; i < nv; ++i) vd[i] = (double)vel_phys[i];
@@ -836,19 +997,27 @@ int or_precond(void *p, const double *r, double *z)
     return OR_OK;
 }
 
-/* Outer FGMRES(m_out) on A_h v = b, b = Q_h f, right preconditioned by
- * M_h^{-1} (Algorithm 1), from v = 0.  Each cycle ends when the Arnoldi
- * estimate of the relative residual drops to tol; convergence is decided on
- * the recomputed residual ||b - A_h v|| / ||b|| (eq. relative-residual).
- * Writes u = Q_h v.  Returns 0 when converged, 1 when max_outer
- * preconditioner calls were spent first.  max_outer <= 0 means no limit. */
-int or_solve(void *p, const double *f, double tol, int max_outer, double *u, int *iters, double *relres)
+/* A_h (transposed = 0) or A_h^T (transposed = 1) on level 0 */
+static void outer_apply(const or_hier *H, int transposed, const cplx *x, cplx *y)
 {
-    or_hier *H = (or_hier *)p;
+    if (transposed)
+        level_apply_t(H, &H->lev[0], OP_A, x, y);
+    else
+        level_apply(H, &H->lev[0], OP_A, x, y);
+}
+
+/* v <- outer FGMRES(m_out) for (A_h or A_h^T) v = b from v = 0, right preconditioned by
+ * M_h^{-1} (Algorithm 1).  Each cycle ends when the Arnoldi estimate of the relative
+ * residual drops to tol; convergence is decided on the recomputed residual
+ * ||b - A v|| / ||b|| (eq. relative-residual).  Returns 0 when converged, 1 when
+ * max_outer preconditioner calls were spent first.  max_outer <= 0 means no limit. */
+static int outer_fgmres(const or_hier *H, int transposed, const cplx *b, cplx *v, double tol, int max_outer,
+                        int *iters, double *relres)
+{
     const or_level *L = &H->lev[0];
     size_t n = L->nn;
     int m = H->p.m_out;
-    cplx *b = vnew(n), *v = vnew(n), *r = vnew(n), *w = vnew(n);
+    cplx *r = vnew(n), *w = vnew(n);
     cplx **V = (cplx **)calloc((size_t)m + 1, sizeof(cplx *));
     cplx **Z = (cplx **)calloc((size_t)m, sizeof(cplx *));
     for (int j = 0; j <= m; ++j) V[j] = vnew(n);
@@ -858,15 +1027,19 @@ int or_solve(void *p, const double *f, double tol, int max_outer, double *u, int
     cplx *sn = (cplx *)calloc((size_t)m, sizeof(cplx));
     cplx *gv = (cplx *)calloc((size_t)m + 1, sizeof(cplx));
     cplx *yv = (cplx *)calloc((size_t)m, sizeof(cplx));
-    level_apply(H, L, OP_Q, (const cplx *)f, b);
+    vzero(n, v);
     double bn = vnorm(n, b);
     int its = 0, status = 0;
     double rel = 0.0;
-    if (bn == 0.0) {
-        vzero(n, v);
-    } else {
+    if (bn > 0.0) {
         for (;;) {
-            level_residual(H, L, OP_A, b, v, r);
+            outer_apply(H, transposed, v, r);   /* r = b - A v, zero on the boundary */
+            for (int z = 0; z <= L->n[2]; ++z)
+                for (int y = 0; y <= L->n[1]; ++y)
+                    for (int x = 0; x <= L->n[0]; ++x) {
+                        size_t i = idx3(L->n, x, y, z);
+                        r[i] = on_boundary(L->n, x, y, z) ? 0 : b[i] - r[i];
+                    }
             double beta = vnorm(n, r);
             rel = beta / bn;
             if (rel <= tol) break;
@@ -882,7 +1055,7 @@ int or_solve(void *p, const double *f, double tol, int max_outer, double *u, int
             for (int k = 0; k < m; ++k) {
                 precond(H, V[k], Z[k]);
                 ++its;
-                level_apply(H, L, OP_A, Z[k], w);
+                outer_apply(H, transposed, Z[k], w);
                 for (int j = 0; j <= k; ++j) {
                     cplx hjk = vdot(n, V[j], w);
                     Hm[j * m + k] = hjk;
@@ -926,7 +1099,6 @@ int or_solve(void *p, const double *f, double tol, int max_outer, double *u, int
             for (int j = 0; j < kk; ++j) vaxpy(n, yv[j], Z[j], v);
         }
     }
-    level_apply(H, L, OP_Q, v, (cplx *)u);
     *iters = its;
     *relres = rel;
     for (int j = 0; j <= m; ++j) free(V[j]);
@@ -938,9 +1110,91 @@ int or_solve(void *p, const double *f, double tol, int max_outer, double *u, int
     free(sn);
     free(gv);
     free(yv);
-    free(b);
-    free(v);
     free(r);
     free(w);
     return status;
+}
+
+/* Outer FGMRES(m_out) for A_h v = Q_h f (eq. iofd-complete-system), right preconditioned by
+ * M_h^{-1} (Algorithm 1), from v = 0 (see outer_fgmres).  Writes u = Q_h v.  Returns 0
+ * when converged, 1 when max_outer preconditioner calls were spent first. */
+int or_solve(void *p, const double *f, double tol, int max_outer, double *u, int *iters, double *relres)
+{
+    or_hier *H = (or_hier *)p;
+    const or_level *L = &H->lev[0];
+    size_t n = L->nn;
+    cplx *b = vnew(n), *v = vnew(n);
+    level_apply(H, L, OP_Q, (const cplx *)f, b);
+    int status = outer_fgmres(H, 0, b, v, tol, max_outer, iters, relres);
+    level_apply(H, L, OP_Q, v, (cplx *)u);
+    free(b);
+    free(v);
+    return status;
+}
+
+/* y = op^T x (op A or B on any level, Q on level 0) */
+int or_apply_t(void *p, int level, int op, const double *x, double *y)
+{
+    or_hier *H = (or_hier *)p;
+    if (level < 0 || level > 2 || (op != OP_A && op != OP_B && op != OP_Q) || (op == OP_Q && level != 0))
+        return OR_EINVAL;
+    level_apply_t(H, &H->lev[level], op, (const cplx *)x, (cplx *)y);
+    return OR_OK;
+}
+
+/* y_i = (d_i op x)_i on level 0, op A or Q (derivative of row i in m_i = 1/c_i^2) */
+int or_apply_dm(void *p, int op, const double *x, double *y)
+{
+    or_hier *H = (or_hier *)p;
+    if (op != OP_A && op != OP_Q) return OR_EINVAL;
+    level_apply_dm(H, op, (const cplx *)x, (cplx *)y);
+    return OR_OK;
+}
+
+/* Gradient of a misfit J(u), u = Q_h v, A_h v = Q_h f, with respect to the squared slowness
+ * m = 1/c^2 at the physical nodes, for the adjoint source s (dJ = Re sum_i conj(s_i) du_i).
+ * Differentiating the state equation: du = dQ v + Q dv and A dv = dQ f - dA v, so with
+ * A^T mu = Q^T conj(s),
+ *   dJ = Re sum_i dm_i [ conj(s_i) (d_i Q v)_i + mu_i ((d_i Q f)_i - (d_i A v)_i) ],
+ * every row depending on the m of its own node.  A PML node carries the m of its nearest
+ * physical node, so its term adds onto that node.  Both solves run to tol.  iters and
+ * relres receive the forward then the adjoint counts. */
+int or_grad(void *p, const double *f, const double *s, double tol, double *grad_phys, int *iters, double *relres)
+{
+    or_hier *H = (or_hier *)p;
+    const or_level *L = &H->lev[0];
+    size_t n = L->nn;
+    const cplx *fv = (const cplx *)f, *sv = (const cplx *)s;
+    cplx *b = vnew(n), *v = vnew(n), *mu = vnew(n), *sc = vnew(n);
+    cplx *dAv = vnew(n), *dQv = vnew(n), *dQf = vnew(n);
+    level_apply(H, L, OP_Q, fv, b);
+    int st = outer_fgmres(H, 0, b, v, tol, 0, &iters[0], &relres[0]);
+    for (size_t i = 0; i < n; ++i) sc[i] = conj(sv[i]);
+    level_apply_t(H, L, OP_Q, sc, b);                   /* Q^T conj(s) */
+    st |= outer_fgmres(H, 1, b, mu, tol, 0, &iters[1], &relres[1]);
+    level_apply_dm(H, OP_A, v, dAv);
+    level_apply_dm(H, OP_Q, v, dQv);
+    level_apply_dm(H, OP_Q, fv, dQf);
+    const int *np = H->nphys;
+    memset(grad_phys, 0, sizeof(double) * (size_t)(np[0] + 1) * (np[1] + 1) * (np[2] + 1));
+    for (int z = 1; z < L->n[2]; ++z)
+        for (int y = 1; y < L->n[1]; ++y)
+            for (int x = 1; x < L->n[0]; ++x) {
+                size_t i = idx3(L->n, x, y, z);
+                double gi = creal(conj(sv[i]) * dQv[i] + mu[i] * (dQf[i] - dAv[i]));
+                int q[3] = {x - H->n_pml, y - H->n_pml, z - H->n_pml};
+                for (int a = 0; a < 3; ++a) {
+                    if (q[a] < 0) q[a] = 0;
+                    if (q[a] > np[a]) q[a] = np[a];
+                }
+                grad_phys[((size_t)q[2] * (np[1] + 1) + q[1]) * (np[0] + 1) + q[0]] += gi;
+            }
+    free(b);
+    free(v);
+    free(mu);
+    free(sc);
+    free(dAv);
+    free(dQv);
+    free(dQf);
+    return st;
 }

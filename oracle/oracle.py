@@ -62,6 +62,9 @@ def lib():
             getattr(L, name).argtypes = [P, P, P]
         L.or_smooth.argtypes = [P, P, P, P]
         L.or_solve.argtypes = [P, P, D, I, P, P, P]
+        L.or_apply_t.argtypes = [P, I, I, P, P]
+        L.or_apply_dm.argtypes = [P, I, P, P]
+        L.or_grad.argtypes = [P, P, P, D, P, P, P]
         _lib = L
     return _lib
 
@@ -208,3 +211,28 @@ class Hierarchy:
         st = lib().or_solve(self._p, f.ctypes.data, float(tol), int(max_outer), u.ctypes.data,
                             ctypes.byref(its), ctypes.byref(rel))
         return u, int(its.value), float(rel.value), int(st)
+
+    def apply_t(self, level, op, x):
+        """op^T x (op A or B on any level, Q on level 0)."""
+        x = _c(x)
+        y = self.zeros(level)
+        assert lib().or_apply_t(self._p, level, op, x.ctypes.data, y.ctypes.data) == 0
+        return y
+
+    def apply_dm(self, op, x):
+        """y_i = (d op / d m_i x)_i on the fine level (op A or Q), m = 1/c^2."""
+        x = _c(x)
+        y = self.zeros(0)
+        assert lib().or_apply_dm(self._p, op, x.ctypes.data, y.ctypes.data) == 0
+        return y
+
+    def grad(self, f, s, tol):
+        """dJ/dm at the physical nodes for the adjoint source s (dJ = Re sum conj(s) du)."""
+        f, s = _c(f), _c(s)
+        nx, ny, nz = self.phys
+        g = np.zeros((nz + 1, ny + 1, nx + 1), dtype=np.float64)
+        its = np.zeros(2, dtype=np.int32)
+        rel = np.zeros(2, dtype=np.float64)
+        st = lib().or_grad(self._p, f.ctypes.data, s.ctypes.data, float(tol), g.ctypes.data, its.ctypes.data,
+                           rel.ctypes.data)
+        return g, its, rel, int(st)
