@@ -64,7 +64,12 @@ typedef enum {
     HELM_OP_B = 1,      /* B_l = L_l - (1 + i sigma) M_l (eq. shifted-iofd-levels) */
     HELM_OP_Q = 2,      /* amplitude correction Q_h, level 0 only (eq. q-operator) */
     HELM_OP_DIAG_A = 3, /* y = diag(A_l) x */
-    HELM_OP_DIAG_B = 4  /* y = diag(B_l) x */
+    HELM_OP_DIAG_B = 4, /* y = diag(B_l) x */
+    HELM_OP_AT = 5,     /* y = A_l^T x (transpose, not conjugate transpose) */
+    HELM_OP_BT = 6,     /* y = B_l^T x */
+    HELM_OP_QT = 7,     /* y = Q_h^T x, level 0 only */
+    HELM_OP_DA = 8,     /* y_i = (d A_h / d m_i x)_i, m = 1/c^2 at node i, level 0 only */
+    HELM_OP_DQ = 9      /* y_i = (d Q_h / d m_i x)_i, level 0 only */
 } helm_op;
 
 /* Solver configuration.  helm_default_options() fills the fixed
@@ -126,9 +131,29 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
 helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, int *iters,
                        double *relres);
 
-/* Misfit gradient with respect to squared slowness (adjoint solve through the
- * same hierarchy).  Not available in this version: returns HELM_ENOTIMPL. */
-helm_status helm_grad(helm_hierarchy *H, const void *adj_src, int nrhs, double tol, float *grad_m);
+/* Gradient of a real misfit J(u) of the solutions u = Q_h v, A_h v = Q_h f
+ * (eq. iofd-complete-system), with respect to the squared slowness m = 1/c^2
+ * at the physical nodes, by the adjoint state.  Each row of A_h and Q_h takes
+ * its coefficients at its own node (Sec. 2.2: kappa and eta* at the row
+ * centre), so with A_h^T mu = Q_h^T conj(s),
+ *   dJ/dm_i = Re[ conj(s_i) (d_i Q_h v)_i + mu_i ((d_i Q_h f)_i - (d_i A_h v)_i) ],
+ * and a PML node, which takes the velocity of its nearest physical node
+ * (Sec. 2.1), adds its term onto that node.  Per right-hand side: one forward
+ * and one adjoint solve (outer FGMRES with A_h^T, the same preconditioner),
+ * each to the true relative residual tol.
+ *   f, adj_src DEVICE [nrhs][total grid] precision vectors: sources, and the
+ *              adjoint sources s defined by dJ = Re sum_i conj(s_i) du_i
+ *              (for J = 1/2 ||u - d||^2: s = u - d)
+ *   grad_m     DEVICE float[(nz+1)(ny+1)(nx+1)], physical nodes: dJ/dm summed
+ *              over the right-hand sides (overwritten)
+ *   workspace  DEVICE, >= helm_grad_workspace_size() bytes, 256-byte aligned
+ *   iters, relres HOST [2 nrhs]: preconditioner calls and final true relative
+ *              residuals, forward then adjoint, per right-hand side
+ * Returns HELM_NOT_CONVERGED (gradient still written) if a solve spent
+ * max_outer preconditioner calls. */
+helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes);
+helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int nrhs, double tol, float *grad_m,
+                      void *workspace, size_t ws_bytes, int *iters, double *relres);
 
 void helm_destroy(helm_hierarchy *H);
 
@@ -142,7 +167,7 @@ helm_status helm_dims(const helm_hierarchy *H, int level, int dims[3]);
  *      and the benchmark).  All vectors are DEVICE precision vectors of the
  *      named level; inputs must have zero boundary entries where stated. ---- */
 
-/* y = op x on level (helm_op; HELM_OP_Q only on level 0).  x, y must differ. */
+/* y = op x on level (helm_op; HELM_OP_Q, QT, DA, DQ only on level 0).  x, y must differ. */
 helm_status helm_apply(helm_hierarchy *H, int level, int op, const void *x, void *y);
 
 /* r = g - op x (op = HELM_OP_A or HELM_OP_B); boundary entries of r are zero. */

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhelm.so")
-SOURCES = ["stencil.hip", "transfer.hip", "vector.hip", "helm.hip"]
+SOURCES = ["stencil.hip", "transfer.hip", "vector.hip", "adjoint.hip", "helm.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,418 @@
+// Adjoint-state gradient of a misfit of u = Q_h v, A_h v = Q_h f, with respect
+// to the squared slowness m = 1/c^2 (Sec. 2.2 fixes that every row of A_h and
+// Q_h takes its coefficients at its own node, so d/dm_i touches row i only):
+//   transposed operators A^T, B^T (any level) and Q_h^T, gathered per output
+//   node from the rows of its 27 neighbours (tensor form, eq. iofd-pml rows);
+//   the derivative of row i in m_i applied to a vector;
+//   the gradient terms conj(s_i)(d_i Q v)_i + mu_i ((d_i Q f)_i - (d_i A v)_i)
+//   accumulated in FP64, then summed onto the physical nodes (a PML node takes
+//   the velocity of its nearest physical node, Sec. 2.1).
+// These kernels are off the preconditioner's hot path: one thread per node,
+// every coefficient evaluated where it is needed.
+#include "helm_internal.h"
+
+namespace helm {
+namespace {
+
+template <typename T>
+using real_of = decltype(T{}.re);
+
+template <typename R>
+struct Zc {
+    R r, i;
+};
+
+constexpr int kTX = 64, kTY = 4;
+
+dim3 node_grid3(const Geom &g) {
+    return dim3((unsigned)((g.n[0] + kTX) / kTX), (unsigned)((g.n[1] + kTY) / kTY), (unsigned)(g.n[2] + 1));
+}
+
+template <typename R, typename T>
+__device__ __forceinline__ Zc<R> load(const T *p, long long i) {
+    const T v = p[i];
+    return {(R)v.re, (R)v.im};
+}
+
+// Coefficient functions at a node with velocity c on the level of L:
+// kappa = omega ell / c, eta = min(kappa / 2pi, 0.4) (eq. iofd-clamped-coordinate),
+// the Hermite interval k and local variable t.  de = d eta / d m (0 on the clamp).
+template <typename R>
+struct Loc {
+    R kappa, t, de;
+    int k;
+};
+
+template <typename R>
+__device__ __forceinline__ Loc<R> locate_at(const LevelArgs<R> &L, float c) {
+    Loc<R> o;
+    const R cc = (R)c;
+    o.kappa = L.omega_ell / cc;
+    R eta = o.kappa * (R)0.15915494309189533577;   // 1 / (2 pi)
+    const bool clamped = !(eta < (R)0.4);
+    if (clamped) eta = (R)0.4;
+    // kappa = omega ell sqrt(m): d kappa / d m = kappa c^2 / 2
+    o.de = clamped ? (R)0 : o.kappa * cc * cc * (R)0.07957747154594766788;   // / (4 pi)
+    const R u = eta * L.inv_deta;
+    int k = (int)u;
+    k = k < L.K - 1 ? k : L.K - 1;
+    k = k > 0 ? k : 0;
+    o.k = k;
+    o.t = u - (R)k;
+    return o;
+}
+
+template <typename R>
+__device__ __forceinline__ R hval(const R *p, R t) { return ((p[3] * t + p[2]) * t + p[1]) * t + p[0]; }
+template <typename R>
+__device__ __forceinline__ R hdt(const R *p, R t) { return ((R)3 * p[3] * t + (R)2 * p[2]) * t + p[1]; }
+
+// transverse weights T[nz] (a4, a5/4, (1-a4-a5)/4) and mass weights M[shell]
+// (a1, a2/6, a3/12, (1-a1-a2-a3)/8) of row i, kappa^2 of row i
+template <typename R>
+struct RowW {
+    R T[3], M[4], k2;
+};
+
+template <typename R>
+__device__ __forceinline__ RowW<R> row_weights(const LevelArgs<R> &L, float c) {
+    const Loc<R> q = locate_at(L, c);
+    const R *p = L.atab + q.k * 20;
+    R a[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) a[f] = hval(p + 4 * f, q.t);
+    RowW<R> w;
+    w.T[0] = a[3];
+    w.T[1] = a[4] * (R)0.25;
+    w.T[2] = ((R)1 - a[3] - a[4]) * (R)0.25;
+    w.M[0] = a[0];
+    w.M[1] = a[1] * (R)(1.0 / 6);
+    w.M[2] = a[2] * (R)(1.0 / 12);
+    w.M[3] = ((R)1 - a[0] - a[1] - a[2]) * (R)0.125;
+    w.k2 = q.kappa * q.kappa;
+    return w;
+}
+
+// derivatives in m of the same weights (dk2 = d kappa^2 / dm = kappa^2 c^2) and the
+// Q_h shell weights' derivatives (b1, b2/6, b3/12, (1-b1-b2-b3)/8)
+template <typename R>
+struct RowD {
+    R dT[3], dM[4], M[4], k2, dk2, dQ[4];
+};
+
+template <typename R>
+__device__ __forceinline__ RowD<R> row_derivs(const LevelArgs<R> &L, float c) {
+    const Loc<R> q = locate_at(L, c);
+    const R *p = L.atab + q.k * 20;
+    const R *pb = L.btab + q.k * 12;
+    const R dt = L.inv_deta * q.de;   // d t / d m
+    R a[5], da[5], db[3];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        a[f] = hval(p + 4 * f, q.t);
+        da[f] = hdt(p + 4 * f, q.t) * dt;
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) db[f] = hdt(pb + 4 * f, q.t) * dt;
+    RowD<R> d;
+    d.dT[0] = da[3];
+    d.dT[1] = da[4] * (R)0.25;
+    d.dT[2] = -(da[3] + da[4]) * (R)0.25;
+    d.M[0] = a[0];
+    d.M[1] = a[1] * (R)(1.0 / 6);
+    d.M[2] = a[2] * (R)(1.0 / 12);
+    d.M[3] = ((R)1 - a[0] - a[1] - a[2]) * (R)0.125;
+    d.dM[0] = da[0];
+    d.dM[1] = da[1] * (R)(1.0 / 6);
+    d.dM[2] = da[2] * (R)(1.0 / 12);
+    d.dM[3] = -(da[0] + da[1] + da[2]) * (R)0.125;
+    d.k2 = q.kappa * q.kappa;
+    const R cc = (R)c;
+    d.dk2 = d.k2 * cc * cc;
+    d.dQ[0] = db[0];
+    d.dQ[1] = db[1] * (R)(1.0 / 6);
+    d.dQ[2] = db[2] * (R)(1.0 / 12);
+    d.dQ[3] = -(db[0] + db[1] + db[2]) * (R)0.125;
+    return d;
+}
+
+// second-difference weight of axis j at node coordinate a for offset d in {-1, 0, 1}
+template <typename R>
+__device__ __forceinline__ Zc<R> axis_w(const R *w, int a, int d) {
+    const R *p = w + 6 * a + 2 * (d + 1);
+    return {p[0], p[1]};
+}
+
+template <typename R>
+__device__ __forceinline__ bool inside(const LevelArgs<R> &L, int x, int y, int z) {
+    return x >= 1 && x <= L.nx - 1 && y >= 1 && y <= L.ny - 1 && z >= 1 && z <= L.nz - 1;
+}
+
+// y = op^T x (op A, or B with SHIFT), optionally y = g - op^T x (RESID; zero on the boundary).
+// Entry (i, k) of op, i = k + delta, is row i's coefficient for the offset -delta:
+// sum_j w_j(i_j, -delta_j) T_i[nonzeros of delta off axis j] - mu kappa_i^2 M_i[|delta|_1].
+template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID>
+__global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
+                                                TY *__restrict__ y) {
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
+    if (X > L.nx || Y > L.ny) return;
+    const long long k = (long long)Zz * L.sy + (long long)Y * L.sx + X;
+    Zc<R> acc = {0, 0};
+    const bool in = inside(L, X, Y, Zz);
+    if (in) {
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xi = X + dx, yi = Y + dy, zi = Zz + dz;
+                    if (!inside(L, xi, yi, zi)) continue;
+                    const long long i = k + dx + (long long)dy * L.sx + (long long)dz * L.sy;
+                    const RowW<R> w = row_weights(L, L.c[i]);
+                    const int d[3] = {dx, dy, dz}, pos[3] = {xi, yi, zi};
+                    const R *ws[3] = {L.wx, L.wy, L.wz};
+                    Zc<R> cf = {0, 0};
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int nz = (j != 0 && dx != 0) + (j != 1 && dy != 0) + (j != 2 && dz != 0);
+                        const Zc<R> wj = axis_w(ws[j], pos[j], -d[j]);
+                        cf.r += wj.r * w.T[nz];
+                        cf.i += wj.i * w.T[nz];
+                    }
+                    const R km = w.k2 * w.M[(dx != 0) + (dy != 0) + (dz != 0)];
+                    cf.r -= km;
+                    if (SHIFT) cf.i -= L.sigma * km;
+                    const Zc<R> xv = load<R>(x, i);
+                    acc.r += cf.r * xv.r - cf.i * xv.i;
+                    acc.i += cf.r * xv.i + cf.i * xv.r;
+                }
+        acc.r *= L.inv_ell2;
+        acc.i *= L.inv_ell2;
+    }
+    TY o;
+    if (RESID) {
+        const Zc<R> gv = in ? load<R>(g, k) : Zc<R>{0, 0};
+        o.re = (real_of<TY>)(gv.r - acc.r);
+        o.im = (real_of<TY>)(gv.i - acc.i);
+    } else {
+        o.re = (real_of<TY>)acc.r;
+        o.im = (real_of<TY>)acc.i;
+    }
+    y[k] = o;
+}
+
+// y = Q_h^T w (CONJ: of conj(w)); row i of Q_h has the shell weights of its own node
+// (eq. q-operator) on its interior neighbours.
+template <typename R, typename TI, typename TO, bool CONJ>
+__global__ void __launch_bounds__(256) k_qapply_t(LevelArgs<R> L, const TI *__restrict__ w, TO *__restrict__ y) {
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
+    if (X > L.nx || Y > L.ny) return;
+    const long long k = (long long)Zz * L.sy + (long long)Y * L.sx + X;
+    Zc<R> acc = {0, 0};
+    if (inside(L, X, Y, Zz)) {
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (!inside(L, X + dx, Y + dy, Zz + dz)) continue;
+                    const long long i = k + dx + (long long)dy * L.sx + (long long)dz * L.sy;
+                    const Loc<R> q = locate_at(L, L.c[i]);
+                    const R *pb = L.btab + q.k * 12;
+                    const R b1 = hval(pb, q.t), b2 = hval(pb + 4, q.t), b3 = hval(pb + 8, q.t);
+                    const int sh = (dx != 0) + (dy != 0) + (dz != 0);
+                    const R qm = sh == 0 ? b1 : sh == 1 ? b2 * (R)(1.0 / 6)
+                                              : sh == 2 ? b3 * (R)(1.0 / 12) : ((R)1 - b1 - b2 - b3) * (R)0.125;
+                    Zc<R> v = load<R>(w, i);
+                    if (CONJ) v.i = -v.i;
+                    acc.r += qm * v.r;
+                    acc.i += qm * v.i;
+                }
+    }
+    TO o;
+    o.re = (real_of<TO>)acc.r;
+    o.im = (real_of<TO>)acc.i;
+    y[k] = o;
+}
+
+// (d_i A x)_i and (d_i Q x)_i at an interior node
+template <typename R, typename T>
+__device__ __forceinline__ Zc<R> row_dA(const LevelArgs<R> &L, const RowD<R> &d, int X, int Y, int Zz, long long k,
+                                        const T *x) {
+    Zc<R> acc = {0, 0};
+    const int pos[3] = {X, Y, Zz};
+    const R *ws[3] = {L.wx, L.wy, L.wz};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!inside(L, X + dx, Y + dy, Zz + dz)) continue;
+                const int dd[3] = {dx, dy, dz};
+                Zc<R> cf = {0, 0};
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int nz = (j != 0 && dx != 0) + (j != 1 && dy != 0) + (j != 2 && dz != 0);
+                    const Zc<R> wj = axis_w(ws[j], pos[j], dd[j]);
+                    cf.r += wj.r * d.dT[nz];
+                    cf.i += wj.i * d.dT[nz];
+                }
+                const int sh = (dx != 0) + (dy != 0) + (dz != 0);
+                cf.r -= d.dk2 * d.M[sh] + d.k2 * d.dM[sh];
+                const Zc<R> xv = load<R>(x, k + dx + (long long)dy * L.sx + (long long)dz * L.sy);
+                acc.r += cf.r * xv.r - cf.i * xv.i;
+                acc.i += cf.r * xv.i + cf.i * xv.r;
+            }
+    acc.r *= L.inv_ell2;
+    acc.i *= L.inv_ell2;
+    return acc;
+}
+
+template <typename R, typename T>
+__device__ __forceinline__ Zc<R> row_dQ(const LevelArgs<R> &L, const RowD<R> &d, int X, int Y, int Zz, long long k,
+                                        const T *x) {
+    Zc<R> acc = {0, 0};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!inside(L, X + dx, Y + dy, Zz + dz)) continue;
+                const R qm = d.dQ[(dx != 0) + (dy != 0) + (dz != 0)];
+                const Zc<R> xv = load<R>(x, k + dx + (long long)dy * L.sx + (long long)dz * L.sy);
+                acc.r += qm * xv.r;
+                acc.i += qm * xv.i;
+            }
+    return acc;
+}
+
+// y_i = (d_i op x)_i (op A: WHICH 0, Q_h: WHICH 1) on level 0; zero on the boundary
+template <typename R, typename T, int WHICH>
+__global__ void __launch_bounds__(256) k_apply_dm(LevelArgs<R> L, const T *__restrict__ x, T *__restrict__ y) {
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
+    if (X > L.nx || Y > L.ny) return;
+    const long long k = (long long)Zz * L.sy + (long long)Y * L.sx + X;
+    Zc<R> v = {0, 0};
+    if (inside(L, X, Y, Zz)) {
+        const RowD<R> d = row_derivs(L, L.c[k]);
+        v = WHICH == 0 ? row_dA(L, d, X, Y, Zz, k, x) : row_dQ(L, d, X, Y, Zz, k, x);
+    }
+    T o;
+    o.re = (real_of<T>)v.r;
+    o.im = (real_of<T>)v.i;
+    y[k] = o;
+}
+
+// gacc_i += Re[ conj(s_i) (d_i Q v)_i + mu_i ((d_i Q f)_i - (d_i A v)_i) ] at interior nodes
+template <typename TS>
+__global__ void __launch_bounds__(256) k_grad_node(LevelArgs<double> L, const c64 *__restrict__ v,
+                                                  const c64 *__restrict__ mu, const TS *__restrict__ s,
+                                                  const TS *__restrict__ f, double *__restrict__ gacc) {
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
+    if (X > L.nx || Y > L.ny || !inside(L, X, Y, Zz)) return;
+    const long long k = (long long)Zz * L.sy + (long long)Y * L.sx + X;
+    const RowD<double> d = row_derivs(L, L.c[k]);
+    const Zc<double> dAv = row_dA(L, d, X, Y, Zz, k, v);
+    const Zc<double> dQv = row_dQ(L, d, X, Y, Zz, k, v);
+    const Zc<double> dQf = row_dQ(L, d, X, Y, Zz, k, f);
+    const Zc<double> si = load<double>(s, k), mi = load<double>(mu, k);
+    const double tr = dQf.r - dAv.r, ti = dQf.i - dAv.i;
+    gacc[k] += (si.r * dQv.r + si.i * dQv.i) + (mi.r * tr - mi.i * ti);
+}
+
+// out_p = sum of gacc over the total-grid nodes whose nearest physical node is p
+__global__ void __launch_bounds__(256) k_grad_phys(const double *__restrict__ gacc, Geom F, int n_pml, int nxp,
+                                                  int nyp, int nzp, float *__restrict__ out) {
+    const int px = blockIdx.x * kTX + threadIdx.x, py = blockIdx.y * kTY + threadIdx.y, pz = blockIdx.z;
+    if (px > nxp || py > nyp || pz > nzp) return;
+    auto range = [n_pml](int p, int np, int &lo, int &hi) {
+        lo = p == 0 ? 0 : p + n_pml;
+        hi = p == np ? np + 2 * n_pml : p + n_pml;
+    };
+    int x0, x1, y0, y1, z0, z1;
+    range(px, nxp, x0, x1);
+    range(py, nyp, y0, y1);
+    range(pz, nzp, z0, z1);
+    double sacc = 0.0;
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) sacc += gacc[(long long)z * F.sy + (long long)y * F.sx + x];
+    out[((long long)pz * (nyp + 1) + py) * (nxp + 1) + px] = (float)sacc;
+}
+
+}  // namespace
+
+template <typename R, typename TX, typename TG, typename TY>
+hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s) {
+    Geom gm{};
+    gm.n[0] = L.nx;
+    gm.n[1] = L.ny;
+    gm.n[2] = L.nz;
+    const dim3 grid = node_grid3(gm), blk(kTX, kTY);
+    if (g) {
+        if (shifted)
+            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, true, true>), grid, blk, 0, s, L, x, g, y);
+        else
+            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, false, true>), grid, blk, 0, s, L, x, g, y);
+    } else {
+        if (shifted)
+            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, true, false>), grid, blk, 0, s, L, x, g, y);
+        else
+            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, false, false>), grid, blk, 0, s, L, x, g, y);
+    }
+    return hipGetLastError();
+}
+
+template <typename R, typename TI, typename TO>
+hipError_t launch_qapply_t(const LevelArgs<R> &L, const TI *w, bool conj_in, TO *y, hipStream_t s) {
+    Geom gm{};
+    gm.n[0] = L.nx;
+    gm.n[1] = L.ny;
+    gm.n[2] = L.nz;
+    if (conj_in)
+        hipLaunchKernelGGL((k_qapply_t<R, TI, TO, true>), node_grid3(gm), dim3(kTX, kTY), 0, s, L, w, y);
+    else
+        hipLaunchKernelGGL((k_qapply_t<R, TI, TO, false>), node_grid3(gm), dim3(kTX, kTY), 0, s, L, w, y);
+    return hipGetLastError();
+}
+
+template <typename R, typename T>
+hipError_t launch_apply_dm(const LevelArgs<R> &L, int which, const T *x, T *y, hipStream_t s) {
+    Geom gm{};
+    gm.n[0] = L.nx;
+    gm.n[1] = L.ny;
+    gm.n[2] = L.nz;
+    if (which == 0)
+        hipLaunchKernelGGL((k_apply_dm<R, T, 0>), node_grid3(gm), dim3(kTX, kTY), 0, s, L, x, y);
+    else
+        hipLaunchKernelGGL((k_apply_dm<R, T, 1>), node_grid3(gm), dim3(kTX, kTY), 0, s, L, x, y);
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_grad_node(const LevelArgs<double> &L, const c64 *v, const c64 *mu, const TS *s_, const TS *f,
+                            double *gacc, hipStream_t s) {
+    Geom gm{};
+    gm.n[0] = L.nx;
+    gm.n[1] = L.ny;
+    gm.n[2] = L.nz;
+    hipLaunchKernelGGL((k_grad_node<TS>), node_grid3(gm), dim3(kTX, kTY), 0, s, L, v, mu, s_, f, gacc);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, const int nphys[3], float *out,
+                            hipStream_t s) {
+    const dim3 grid((unsigned)((nphys[0] + kTX) / kTX), (unsigned)((nphys[1] + kTY) / kTY), (unsigned)(nphys[2] + 1));
+    hipLaunchKernelGGL(k_grad_phys, grid, dim3(kTX, kTY), 0, s, gacc, fine, n_pml, nphys[0], nphys[1], nphys[2], out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_apply_t<float, c32, c32, c32>(const LevelArgs<float> &, int, const c32 *, const c32 *,
+                                                         c32 *, hipStream_t);
+template hipError_t launch_apply_t<double, c64, c64, c64>(const LevelArgs<double> &, int, const c64 *, const c64 *,
+                                                          c64 *, hipStream_t);
+template hipError_t launch_qapply_t<double, c32, c64>(const LevelArgs<double> &, const c32 *, bool, c64 *,
+                                                      hipStream_t);
+template hipError_t launch_qapply_t<double, c64, c64>(const LevelArgs<double> &, const c64 *, bool, c64 *,
+                                                      hipStream_t);
+template hipError_t launch_qapply_t<float, c32, c32>(const LevelArgs<float> &, const c32 *, bool, c32 *, hipStream_t);
+template hipError_t launch_apply_dm<float, c32>(const LevelArgs<float> &, int, const c32 *, c32 *, hipStream_t);
+template hipError_t launch_apply_dm<double, c64>(const LevelArgs<double> &, int, const c64 *, c64 *, hipStream_t);
+template hipError_t launch_grad_node<c32>(const LevelArgs<double> &, const c64 *, const c64 *, const c32 *,
+                                          const c32 *, double *, hipStream_t);
+template hipError_t launch_grad_node<c64>(const LevelArgs<double> &, const c64 *, const c64 *, const c64 *,
+                                          const c64 *, double *, hipStream_t);
+
+}  // namespace helm

@@ -280,6 +280,9 @@ struct Eng {
     Lane *Ln;
     hipStream_t s;
 
+    bool transposed = false;   // outer solve with A_h^T (adjoint); r64: its FP64 residual buffer
+    c64 *r64 = nullptr;
+
     explicit Eng(helm_hierarchy *h, int lane = 0) : H(h), Ln(&h->lane[lane]), s(h->lane[lane].s) {}
 
     const LevelArgs<R> &L(int l) const;
@@ -445,8 +448,31 @@ struct Eng {
         return hipStreamSynchronize(s);
     }
 
-    // Outer FGMRES(m_out) for one right-hand side (Sec. 3.3); x and b in FP64.
+    // Outer FGMRES(m_out) for one right-hand side (Sec. 3.3); x and b in FP64:
+    // b = Q_h f, solve A_h v = b, u = Q_h v (u may be null: v stays in x64).
     helm_status solve_one(const T *f, T *u, double tol, int *iters, double *relres) {
+        HIP_TRY((launch_qapply<double, T, c64>(H->Ld[0], f, Ln->b64, s)));   // b = Q_h f
+        const helm_status status = solve_b64(tol, iters, relres);
+        if (status < 0) return status;
+        if (u) HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], Ln->x64, u, s)));   // u = Q_h v
+        HIP_TRY(hipStreamSynchronize(s));
+        return status;
+    }
+
+    // FP64 true residual r = b - op x64 into V0 (working precision), its norm into the state
+    hipError_t outer_residual(T *V0, KState *st) {
+        if (!transposed) {
+            StencilCall c{M_RESID, 0, 0.0, Ln->x64, Ln->b64, nullptr, V0, true, EPI_NORM_INIT, st, 0};
+            return launch_stencil<double, c64, c64, T>(H->Ld[0], c, Ln->rb, s);
+        }
+        HIP_CHK((launch_apply_t<double, c64, c64, c64>(H->Ld[0], 0, Ln->x64, Ln->b64, r64, s)));
+        HIP_CHK(launch_dots<c64>(nullptr, 0, r64, true, nn(0), EPI_NORM_INIT, st, 0, nullptr, Ln->rb, s));
+        return launch_convert<c64, T>(r64, V0, nn(0), s);
+    }
+
+    // Outer FGMRES(m_out) for op x64 = b64 from x64 = 0 (op = A_h, or A_h^T when transposed),
+    // right preconditioned by Algorithm 1, until the FP64 true relative residual <= tol.
+    helm_status solve_b64(double tol, int *iters, double *relres) {
         const helm_options &o = H->opt;
         const long long n = nn(0);
         T *V[kMMax + 1], *Zp[kMMax];
@@ -454,7 +480,6 @@ struct Eng {
         for (int j = 0; j < o.m_out; ++j) Zp[j] = v(Ln->Zout[j]);
         KState *st = Ln->st_outer;
         const int max_outer = o.max_outer > 0 ? o.max_outer : 1000;
-        HIP_TRY((launch_qapply<double, T, c64>(H->Ld[0], f, Ln->b64, s)));   // b = Q_h f
         HIP_TRY(launch_dots<c64>(nullptr, 0, Ln->b64, true, n, EPI_STORE, nullptr, 0, Ln->dscratch, Ln->rb, s));
         HIP_TRY(hipMemcpyAsync(Ln->host_scratch, Ln->dscratch, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -465,15 +490,13 @@ struct Eng {
         helm_status status = HELM_OK;
         if (!(bn == bn) || bn > 1e300) return fail(H, HELM_BREAKDOWN, "non-finite right-hand side");
         if (bn == 0.0) {
-            HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], Ln->x64, u, s)));
             *iters = 0;
             *relres = 0.0;
             return HELM_OK;
         }
         for (;;) {
-            // true residual in FP64 arithmetic: r = b - A_h x
-            StencilCall c{M_RESID, 0, 0.0, Ln->x64, Ln->b64, nullptr, V[0], true, EPI_NORM_INIT, st, 0};
-            HIP_TRY((launch_stencil<double, c64, c64, T>(H->Ld[0], c, Ln->rb, s)));
+            // true residual in FP64 arithmetic: r = b - op x
+            HIP_TRY(outer_residual(V[0], st));
             HIP_TRY(read_state(st));
             if (Ln->host_state->nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite residual");
             rel = Ln->host_state->beta / bn;
@@ -486,7 +509,10 @@ struct Eng {
             for (int k = 0; k < o.m_out; ++k) {
                 HIP_TRY(precond(V[k], Zp[k]));
                 ++its;
-                HIP_TRY(stencil(0, M_APPLY, false, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
+                if (transposed)
+                    HIP_TRY((launch_apply_t<R, T, T, T>(L(0), 0, Zp[k], (const T *)nullptr, V[k + 1], s)));
+                else
+                    HIP_TRY(stencil(0, M_APPLY, false, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
                 HIP_TRY(arnoldi(0, V, k, st, k == o.m_out - 1));
                 HIP_TRY(read_state(st));
                 kk = k + 1;
@@ -497,8 +523,6 @@ struct Eng {
             }
             HIP_TRY((launch_combine<c64, T>(Ln->x64, (const T *const *)Zp, kk, n, st, true, false, s)));
         }
-        HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], Ln->x64, u, s)));   // u = Q_h v
-        HIP_TRY(hipStreamSynchronize(s));
         *iters = its;
         *relres = rel;
         return status;
@@ -863,8 +887,63 @@ helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, v
     return worst;
 }
 
-helm_status helm_grad(helm_hierarchy *H, const void *, int, double, float *) {
-    return fail(H, HELM_ENOTIMPL, "helm_grad is not available in this version");
+// Gradient workspace: v (c64), the adjoint residual (c64) and the FP64 per-node sums.
+static size_t grad_ws_bytes(const helm_hierarchy *H) {
+    const size_t n = (size_t)H->geom[0].nn;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return 2 * up(n * sizeof(c64)) + up(n * sizeof(double));
+}
+
+helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes) {
+    if (!H || !bytes) return fail(const_cast<helm_hierarchy *>(H), HELM_EINVAL, "invalid workspace-size arguments");
+    *bytes = grad_ws_bytes(H);
+    return HELM_OK;
+}
+
+helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int nrhs, double tol, float *grad_m,
+                      void *workspace, size_t ws_bytes, int *iters, double *relres) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!f || !adj_src || !grad_m || !workspace || !iters || !relres || nrhs < 1 || !(tol > 0) ||
+        !std::isfinite(tol))
+        return fail(H, HELM_EINVAL, "invalid gradient arguments");
+    if (ws_bytes < grad_ws_bytes(H) || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return fail(H, HELM_EWORKSPACE, "gradient workspace too small or not 256-byte aligned");
+    const long long n = H->geom[0].nn;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *w = static_cast<char *>(workspace);
+    c64 *v64 = reinterpret_cast<c64 *>(w);
+    c64 *r64 = reinterpret_cast<c64 *>(w + up(n * sizeof(c64)));
+    double *gacc = reinterpret_cast<double *>(w + 2 * up(n * sizeof(c64)));
+    const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
+    helm_status worst = HELM_OK;
+    auto run = [&](auto E, auto *tag) -> helm_status {
+        using TT = typename std::remove_pointer<decltype(tag)>::type;
+        HIP_TRY((launch_fill_zero<c64>(reinterpret_cast<c64 *>(gacc), n / 2, E.s)));   // n doubles
+        if (n & 1) HIP_TRY(hipMemsetAsync(gacc + n - 1, 0, sizeof(double), E.s));
+        for (int r = 0; r < nrhs; ++r) {
+            const TT *fr = reinterpret_cast<const TT *>(static_cast<const char *>(f) + (size_t)r * n * es);
+            const TT *sr = reinterpret_cast<const TT *>(static_cast<const char *>(adj_src) + (size_t)r * n * es);
+            // forward: A_h v = Q_h f (v kept in FP64)
+            helm_status st = E.solve_one(fr, nullptr, tol, iters + 2 * r, relres + 2 * r);
+            if (st < 0) return st;
+            if (st == HELM_NOT_CONVERGED) worst = st;
+            HIP_TRY((launch_convert<c64, c64>(E.Ln->x64, v64, n, E.s)));
+            // adjoint: A_h^T mu = Q_h^T conj(s)
+            HIP_TRY((launch_qapply_t<double, TT, c64>(H->Ld[0], sr, true, E.Ln->b64, E.s)));
+            E.transposed = true;
+            E.r64 = r64;
+            st = E.solve_b64(tol, iters + 2 * r + 1, relres + 2 * r + 1);
+            E.transposed = false;
+            if (st < 0) return st;
+            if (st == HELM_NOT_CONVERGED) worst = st;
+            HIP_TRY((launch_grad_node<TT>(H->Ld[0], v64, E.Ln->x64, sr, fr, gacc, E.s)));
+        }
+        HIP_TRY(launch_grad_phys(gacc, H->geom[0], H->n_pml, H->nphys, grad_m, E.s));
+        HIP_TRY(hipStreamSynchronize(E.s));
+        return HELM_OK;
+    };
+    helm_status st = (H->prec == HELM_FP64) ? run(Eng<c64>(H, 0), (c64 *)nullptr) : run(Eng<c32>(H, 0), (c32 *)nullptr);
+    return st < 0 ? st : worst;
 }
 
 void helm_destroy(helm_hierarchy *H) {
@@ -883,12 +962,20 @@ helm_status helm_dims(const helm_hierarchy *H, int level, int dims[3]) {
 
 helm_status helm_apply(helm_hierarchy *H, int level, int op, const void *x, void *y) {
     if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
-    if (!level_ok(level) || op < 0 || op > 4 || (op == HELM_OP_Q && level != 0) || !x || !y || x == y)
+    const bool fine_only = op == HELM_OP_Q || op == HELM_OP_QT || op == HELM_OP_DA || op == HELM_OP_DQ;
+    if (!level_ok(level) || op < 0 || op > HELM_OP_DQ || (fine_only && level != 0) || !x || !y || x == y)
         return fail(H, HELM_EINVAL, "invalid apply arguments");
     return dispatch(H, [&](auto E) -> hipError_t {
         using T = typename std::remove_reference<decltype(E)>::type;
         using V = decltype(*E.v(nullptr));
         using TT = typename std::remove_reference<V>::type;
+        using RR = typename T::R;
+        if (op == HELM_OP_AT || op == HELM_OP_BT)
+            return launch_apply_t<RR, TT, TT, TT>(E.L(level), op == HELM_OP_BT, (const TT *)x, (const TT *)nullptr,
+                                                  (TT *)y, E.s);
+        if (op == HELM_OP_QT) return launch_qapply_t<RR, TT, TT>(E.L(0), (const TT *)x, false, (TT *)y, E.s);
+        if (op == HELM_OP_DA || op == HELM_OP_DQ)
+            return launch_apply_dm<RR, TT>(E.L(0), op == HELM_OP_DQ, (const TT *)x, (TT *)y, E.s);
         if (op == HELM_OP_A || op == HELM_OP_B)
             return E.stencil(level, M_APPLY, op == HELM_OP_B, 0.0, x, nullptr, nullptr, y);
         if (op == HELM_OP_Q)

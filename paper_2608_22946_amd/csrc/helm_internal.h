@@ -176,6 +176,22 @@ hipError_t launch_jac1(const LevelArgs<R> &L, int shifted, double omegaJ, const 
 template <typename R>
 hipError_t launch_dinv(const LevelArgs<R> &L, int shifted, R *out, hipStream_t s);   // out = D^-1 per node
 
+// Adjoint gradient (adjoint.hip): y = [g -] op^T x (op A, or B when shifted; g == nullptr:
+// no residual), y = Q_h^T w (of conj(w) when conj_in), y_i = (d_i op x)_i in m = 1/c^2
+// (which 0: A, 1: Q_h), the per-node gradient terms accumulated into gacc, and their sum
+// onto the physical nodes.
+template <typename R, typename TX, typename TG, typename TY>
+hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s);
+template <typename R, typename TI, typename TO>
+hipError_t launch_qapply_t(const LevelArgs<R> &L, const TI *w, bool conj_in, TO *y, hipStream_t s);
+template <typename R, typename T>
+hipError_t launch_apply_dm(const LevelArgs<R> &L, int which, const T *x, T *y, hipStream_t s);
+template <typename TS>
+hipError_t launch_grad_node(const LevelArgs<double> &L, const c64 *v, const c64 *mu, const TS *s_, const TS *f,
+                            double *gacc, hipStream_t s);
+hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, const int nphys[3], float *out,
+                            hipStream_t s);
+
 int stencil_blocks(int nx, int ny, int nz, int tz);   // grid size of launch_stencil on a level (tz 0: default)
 constexpr int kTzCandidates[] = {2, 4, 8, 16, 32, 64};
 

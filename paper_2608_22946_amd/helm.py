@@ -18,6 +18,7 @@ _DEFAULT_TABLE = os.path.join(os.path.dirname(_HERE), "workloads", "iofd_table.j
 
 HELM_OK, HELM_NOT_CONVERGED = 0, 1
 OP_A, OP_B, OP_Q, OP_DIAG_A, OP_DIAG_B = 0, 1, 2, 3, 4
+OP_AT, OP_BT, OP_QT, OP_DA, OP_DQ = 5, 6, 7, 8, 9   # transposes and row derivatives in m = 1/c^2
 FP64, FP32 = 0, 1
 
 _c_int, _c_double, _c_void_p, _c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -34,7 +35,8 @@ class HelmOptions(ctypes.Structure):
                 ("tile_tz", _c_int), ("tile_split", _c_int), ("lanes", _c_int)]
 
 
-EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_grad", "helm_destroy",
+EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_grad",
+            "helm_grad_workspace_size", "helm_destroy",
             "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_residual_restrict", "helm_jacobi",
             "helm_restrict",
             "helm_prolong_add", "helm_bottom", "helm_vcycle", "helm_coarse_solve", "helm_smooth", "helm_precond",
@@ -55,7 +57,8 @@ def lib():
         L.helm_workspace_size.argtypes = [I, I, I, I, ctypes.POINTER(HelmOptions), ctypes.POINTER(_c_size_t)]
         L.helm_setup.argtypes = [P, I, I, I, D, D, I, ctypes.POINTER(HelmOptions), P, _c_size_t, ctypes.POINTER(P)]
         L.helm_solve.argtypes = [P, P, I, D, P, P, P]
-        L.helm_grad.argtypes = [P, P, I, D, P]
+        L.helm_grad.argtypes = [P, P, P, I, D, P, P, _c_size_t, P, P]
+        L.helm_grad_workspace_size.argtypes = [P, ctypes.POINTER(_c_size_t)]
         L.helm_destroy.argtypes = [P]
         L.helm_destroy.restype = None
         L.helm_last_error.argtypes = [P]
@@ -258,6 +261,34 @@ class Hierarchy:
         _check(lib().helm_vec_orthonormalize(self._h, level, k, arr, self._vec(w, level), out.ctypes.data), self._h)
         c = out[0::2] + 1j * out[1::2]
         return c[:k], c[k].real
+
+    def grad(self, f, adj_src, tol):
+        """dJ/dm (m = 1/c^2) at the physical nodes for sources f and adjoint sources s
+        (dJ = Re sum conj(s) du, u = Q v, A v = Q f); f and s of shape (nrhs, ...) or a
+        single grid function.  Returns (float32 gradient on the physical grid, forward
+        and adjoint preconditioner calls [nrhs, 2], true relative residuals [nrhs, 2], rc)."""
+        single = f.dim() == 3
+        fb = f.unsqueeze(0) if single else f
+        sb = adj_src.unsqueeze(0) if single else adj_src
+        for t in (fb, sb):
+            if t.dtype != self.cdtype or tuple(t.shape[1:]) != self.shape(0) or not t.is_contiguous() \
+                    or t.device != self.device:
+                raise ValueError("sources must be contiguous with the level-0 shape and precision dtype")
+        if fb.shape != sb.shape:
+            raise ValueError("f and adj_src must have the same shape")
+        nrhs = fb.shape[0]
+        nbytes = _c_size_t(0)
+        _check(lib().helm_grad_workspace_size(self._h, ctypes.byref(nbytes)), self._h)
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        ws_ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+        nx, ny, nz = self.phys
+        g = torch.empty((nz + 1, ny + 1, nx + 1), dtype=torch.float32, device=self.device)
+        its = np.zeros((nrhs, 2), np.int32)
+        rel = np.zeros((nrhs, 2), np.float64)
+        rc = lib().helm_grad(self._h, _ptr(fb), _ptr(sb), nrhs, float(tol), _ptr(g), _c_void_p(ws_ptr),
+                             nbytes.value, its.ctypes.data, rel.ctypes.data)
+        _check(rc, self._h, allow_not_converged=True)
+        return g, its, rel, rc
 
     def solve(self, f, tol, out=None):
         """u = Q v with A v = Q f; f of shape (nrhs, ...) or a single grid function."""

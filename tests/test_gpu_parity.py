@@ -447,3 +447,59 @@ def test_c2_solve_residual(c2):
     r = p.o.residual(0, 0, b, un)
     true_rel = np.linalg.norm(r) / np.linalg.norm(b)
     assert true_rel <= 1.2e-6, (true_rel, relres, its)
+
+
+# ---- adjoint gradient: transposes, row derivatives in m = 1/c^2, the gradient ----
+
+@pytest.mark.parametrize("level,op", [(0, 5), (0, 6), (0, 7), (1, 5), (1, 6), (2, 6)])
+def test_apply_transposed(pair, level, op):
+    """A^T, B^T (any level) and Q_h^T against the checker's transposes (scatter of rows)."""
+    x = pair.rand(level, 301 + level)
+    y = to_np(pair.g.apply(level, op, pair.dev(x)))
+    ref = pair.o.apply_t(level, op - 5, x.astype(complex))
+    err = rel(y, ref)
+    assert err <= pair.tol(1e-12, 1e-6), err
+
+
+@pytest.mark.parametrize("op", [8, 9])
+def test_apply_row_derivative(pair, op):
+    """y_i = (d_i A_h x)_i and (d_i Q_h x)_i, m = 1/c^2, against the checker."""
+    x = pair.rand(0, 311)
+    y = to_np(pair.g.apply(0, op, pair.dev(x)))
+    ref = pair.o.apply_dm(0 if op == 8 else 2, x.astype(complex))
+    err = rel(y, ref)
+    assert err <= pair.tol(1e-11, 1e-5), err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grad_matches_checker(precision):
+    """dJ/dm at the physical nodes (forward + adjoint solve, row-local assembly, PML
+    nodes summed onto their nearest physical node) against the checker's gradient,
+    whose own central-difference pin is a CPU test; two right-hand sides summed."""
+    vel = grf_velocity(24, 20, 16, seed=41, corr_len=5.0)
+    p = Pair(vel, 4, precision)
+    nx, ny, nz = p.g.dims(0)
+    f = np.stack([point_source((nx, ny, nz), (10, 12, 9), H), point_source((nx, ny, nz), (20, 14, 13), H)])
+    s = np.stack([p.rand(0, 412), p.rand(0, 413)])
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    g, its, rels, rc = p.g.grad(p.dev(f), p.dev(s), tol)
+    assert rc == 0 and rels.max() <= tol, (its, rels)
+    ref = sum(p.o.grad(f[r].astype(complex), s[r].astype(complex), 1e-11)[0] for r in range(2))
+    err = rel(g.cpu().numpy().astype(np.float64), ref)
+    assert err <= (1e-7 if precision == "fp64" else 2e-3), err
+
+
+def test_c2_transpose_identity(c2):
+    """At the full workload size: <A x, y> = <x, A^T y> (bilinear) for the FP32 GPU
+    operators on every level, A and B (FP64 sums of the FP32 results)."""
+    p, _ = c2
+    for level, op in [(0, 0), (1, 1), (2, 1)]:
+        dims = p.g.dims(level)
+        x = torch.from_numpy(random_complex(dims, 500 + level, np.complex64)).cuda()
+        y = torch.from_numpy(random_complex(dims, 600 + level, np.complex64)).cuda()
+        ax = p.g.apply(level, op, x).to(torch.complex128)
+        aty = p.g.apply(level, op + 5, y).to(torch.complex128)
+        lhs = torch.sum(ax * y.to(torch.complex128)).item()
+        rhs = torch.sum(x.to(torch.complex128) * aty).item()
+        scale = (torch.linalg.vector_norm(ax) * torch.linalg.vector_norm(y.to(torch.complex128))).item()
+        assert abs(lhs - rhs) <= 1e-5 * scale, (level, lhs, rhs)
