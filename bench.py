@@ -205,6 +205,76 @@ def multi_rhs(lane_counts=(1, 2, 4), seed=3):
         del Hh, u
 
 
+def grad_bench(steps, warmup, apply_reps, with_cpu):
+    """Adjoint gradient on the benchmark workload: dJ/dm (m = 1/c^2) for the seeded point
+    source and a synthetic adjoint source (seeded complex normal values at every physical
+    (x, y) node of the receiver plane 20 cells below the top of the physical box), i.e. one
+    forward and one adjoint solve to 1e-6 plus the row-local assembly, per step.  Also
+    times the fine-level A_h^T apply (the adjoint's operator).  One JSON line."""
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import load_iofd_table
+
+    vel, omega, f_np, src = workload()
+    table = load_iofd_table()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    Hh = helm.Hierarchy(torch.from_numpy(vel), H, omega, N_PML, precision="fp32", table=table, device=dev)
+    N = N_PHYS + 2 * N_PML
+    zr = N_PML + 20
+    rng = np.random.default_rng(SEED + 100)
+    s_np = np.zeros_like(f_np)
+    s_np[zr, N_PML:N_PML + N_PHYS + 1, N_PML:N_PML + N_PHYS + 1] = (
+        rng.standard_normal((N_PHYS + 1, N_PHYS + 1)) + 1j * rng.standard_normal((N_PHYS + 1, N_PHYS + 1)))
+    f = torch.from_numpy(f_np).to(dev)
+    s = torch.from_numpy(s_np).to(dev)
+    nodes = int(np.prod(Hh.shape(0)))
+
+    x = torch.randn(Hh.shape(0), dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    coef = Hh.row_coefs()
+    for _ in range(3):
+        Hh.apply_t_rows(coef, x, out=y)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(apply_reps):
+        Hh.apply_t_rows(coef, x, out=y)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_at = ev0.elapsed_time(ev1) / 1e3 / apply_reps
+    del x, y, coef
+
+    its = rel = g = None
+    for _ in range(warmup):
+        g, its, rel, rc = Hh.grad(f, s, TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g, its, rel, rc = Hh.grad(f, s, TOL)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    if rc != 0 or not rel.max() <= TOL or not bool(torch.isfinite(g).all()):
+        print(json.dumps({"error": "gradient solves did not reach the tolerance", "relres": rel.tolist()}))
+        sys.exit(1)
+    alg = 40.0 * nodes   # 8 B x + 24 B row coefficients read, 8 B y written per node
+    out = {"metric": "time per misfit gradient dJ/dm (forward + adjoint solve to 1e-6, assembly)",
+           "value": round(dt, 4), "unit": "s per gradient", "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "grf-352-fp32 (as the main line) with a synthetic adjoint source on the "
+                                  f"receiver plane z = {zr}", "source": list(src), "tol": TOL},
+           "pc_calls_forward": int(its[0, 0]), "pc_calls_adjoint": int(its[0, 1]),
+           "relres": [float(v) for v in rel[0]],
+           "roofline": {"bound": "hbm", "kernel": "fine-level A_h^T apply (rows gathered from stored coefficients, 352^3, fp32)",
+                        "achieved": round(alg / t_at / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / t_at / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                        "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_at * 1e3, 4)}}
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline(vel, omega, table, int(its[0, 0]) + int(its[0, 1]))
+        out["cpu_baseline"]["unit"] = "s per gradient (extrapolated)"
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +288,8 @@ def main():
                     help="run the paper's 512^3 Green-function and benchmark-media cases instead (JSON line per case)")
     ap.add_argument("--multi-rhs", action="store_true",
                     help="run the 64-source 288^3 layered workload with 1, 2 and 4 concurrent lanes instead")
+    ap.add_argument("--grad", action="store_true",
+                    help="time the adjoint misfit gradient on the benchmark workload instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see the sharding design).",
@@ -228,6 +300,9 @@ def main():
         return
     if args.multi_rhs:
         multi_rhs()
+        return
+    if args.grad:
+        grad_bench(args.steps, args.warmup, args.apply_reps, not args.no_cpu_baseline)
         return
 
     import torch

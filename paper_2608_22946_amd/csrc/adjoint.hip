@@ -93,6 +93,24 @@ __device__ __forceinline__ RowW<R> row_weights(const LevelArgs<R> &L, float c) {
     return w;
 }
 
+// the same weights from per-node coefficient arrays coef[f * n + i] = (a1..a5, kappa^2)(i)
+template <typename R>
+__device__ __forceinline__ RowW<R> row_weights_pre(const R *__restrict__ coef, long long n, long long i) {
+    R a[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) a[f] = coef[f * n + i];
+    RowW<R> w;
+    w.T[0] = a[3];
+    w.T[1] = a[4] * (R)0.25;
+    w.T[2] = ((R)1 - a[3] - a[4]) * (R)0.25;
+    w.M[0] = a[0];
+    w.M[1] = a[1] * (R)(1.0 / 6);
+    w.M[2] = a[2] * (R)(1.0 / 12);
+    w.M[3] = ((R)1 - a[0] - a[1] - a[2]) * (R)0.125;
+    w.k2 = a[5];
+    return w;
+}
+
 // derivatives in m of the same weights (dk2 = d kappa^2 / dm = kappa^2 c^2) and the
 // Q_h shell weights' derivatives (b1, b2/6, b3/12, (1-b1-b2-b3)/8)
 template <typename R>
@@ -151,9 +169,11 @@ __device__ __forceinline__ bool inside(const LevelArgs<R> &L, int x, int y, int 
 // y = op^T x (op A, or B with SHIFT), optionally y = g - op^T x (RESID; zero on the boundary).
 // Entry (i, k) of op, i = k + delta, is row i's coefficient for the offset -delta:
 // sum_j w_j(i_j, -delta_j) T_i[nonzeros of delta off axis j] - mu kappa_i^2 M_i[|delta|_1].
-template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID>
+// PRE: row weights from coefficient arrays written by k_row_coefs instead of evaluated
+// (27 evaluations per output node otherwise).
+template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID, bool PRE>
 __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
-                                                TY *__restrict__ y) {
+                                                TY *__restrict__ y, const R *__restrict__ coef) {
     const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
     if (X > L.nx || Y > L.ny) return;
     const long long k = (long long)Zz * L.sy + (long long)Y * L.sx + X;
@@ -166,7 +186,8 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
                     const int xi = X + dx, yi = Y + dy, zi = Zz + dz;
                     if (!inside(L, xi, yi, zi)) continue;
                     const long long i = k + dx + (long long)dy * L.sx + (long long)dz * L.sy;
-                    const RowW<R> w = row_weights(L, L.c[i]);
+                    const RowW<R> w = PRE ? row_weights_pre(coef, (long long)(L.nz + 1) * L.sy, i)
+                                          : row_weights(L, L.c[i]);
                     const int d[3] = {dx, dy, dz}, pos[3] = {xi, yi, zi};
                     const R *ws[3] = {L.wx, L.wy, L.wz};
                     Zc<R> cf = {0, 0};
@@ -197,6 +218,19 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
         o.im = (real_of<TY>)acc.i;
     }
     y[k] = o;
+}
+
+// coef[f * n + i] = (a1, .., a5, kappa^2) of row i (interior nodes; boundary rows unused)
+template <typename R>
+__global__ void __launch_bounds__(256) k_row_coefs(LevelArgs<R> L, R *__restrict__ coef) {
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
+    if (X > L.nx || Y > L.ny) return;
+    const long long i = (long long)Zz * L.sy + (long long)Y * L.sx + X, n = (long long)(L.nz + 1) * L.sy;
+    const Loc<R> q = locate_at(L, L.c[i]);
+    const R *p = L.atab + q.k * 20;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) coef[f * n + i] = hval(p + 4 * f, q.t);
+    coef[5 * n + i] = q.kappa * q.kappa;
 }
 
 // y = Q_h^T w (CONJ: of conj(w)); row i of Q_h has the shell weights of its own node
@@ -335,23 +369,33 @@ __global__ void __launch_bounds__(256) k_grad_phys(const double *__restrict__ ga
 }  // namespace
 
 template <typename R, typename TX, typename TG, typename TY>
-hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s) {
+hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s,
+                          const R *coef) {
     Geom gm{};
     gm.n[0] = L.nx;
     gm.n[1] = L.ny;
     gm.n[2] = L.nz;
     const dim3 grid = node_grid3(gm), blk(kTX, kTY);
-    if (g) {
-        if (shifted)
-            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, true, true>), grid, blk, 0, s, L, x, g, y);
-        else
-            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, false, true>), grid, blk, 0, s, L, x, g, y);
+#define HELM_AT(SH, RS, PR) hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, SH, RS, PR>), grid, blk, 0, s, L, x, g, y, coef)
+    if (coef) {
+        if (shifted || g) return hipErrorInvalidValue;   // the coefficient arrays serve the plain A^T apply
+        HELM_AT(false, false, true);
+    } else if (g) {
+        if (shifted) HELM_AT(true, true, false); else HELM_AT(false, true, false);
     } else {
-        if (shifted)
-            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, true, false>), grid, blk, 0, s, L, x, g, y);
-        else
-            hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, false, false>), grid, blk, 0, s, L, x, g, y);
+        if (shifted) HELM_AT(true, false, false); else HELM_AT(false, false, false);
     }
+#undef HELM_AT
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_row_coefs(const LevelArgs<R> &L, R *coef, hipStream_t s) {
+    Geom gm{};
+    gm.n[0] = L.nx;
+    gm.n[1] = L.ny;
+    gm.n[2] = L.nz;
+    hipLaunchKernelGGL((k_row_coefs<R>), node_grid3(gm), dim3(kTX, kTY), 0, s, L, coef);
     return hipGetLastError();
 }
 
@@ -400,9 +444,11 @@ hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, con
 }
 
 template hipError_t launch_apply_t<float, c32, c32, c32>(const LevelArgs<float> &, int, const c32 *, const c32 *,
-                                                         c32 *, hipStream_t);
+                                                         c32 *, hipStream_t, const float *);
 template hipError_t launch_apply_t<double, c64, c64, c64>(const LevelArgs<double> &, int, const c64 *, const c64 *,
-                                                          c64 *, hipStream_t);
+                                                          c64 *, hipStream_t, const double *);
+template hipError_t launch_row_coefs<float>(const LevelArgs<float> &, float *, hipStream_t);
+template hipError_t launch_row_coefs<double>(const LevelArgs<double> &, double *, hipStream_t);
 template hipError_t launch_qapply_t<double, c32, c64>(const LevelArgs<double> &, const c32 *, bool, c64 *,
                                                       hipStream_t);
 template hipError_t launch_qapply_t<double, c64, c64>(const LevelArgs<double> &, const c64 *, bool, c64 *,
