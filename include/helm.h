@@ -170,14 +170,6 @@ helm_status helm_dims(const helm_hierarchy *H, int level, int dims[3]);
 /* y = op x on level (helm_op; HELM_OP_Q, QT, DA, DQ only on level 0).  x, y must differ. */
 helm_status helm_apply(helm_hierarchy *H, int level, int op, const void *x, void *y);
 
-/* coef = the per-node row coefficients of A_h (alpha_1..alpha_5 and kappa^2 at the
- * row centre, Sec. 2.2) as six arrays coef[f * nn + i] over the nn fine nodes, in
- * the working precision (float or double); DEVICE, 6 nn elements. */
-helm_status helm_row_coefs(helm_hierarchy *H, void *coef);
-
-/* y = A_h^T x on level 0 from the row coefficients written by helm_row_coefs: the
- * kernel the adjoint solve of helm_grad uses (HELM_OP_AT evaluates them per use). */
-helm_status helm_apply_t_rows(helm_hierarchy *H, const void *coef, const void *x, void *y);
 
 /* r = g - op x (op = HELM_OP_A or HELM_OP_B); boundary entries of r are zero. */
 helm_status helm_residual(helm_hierarchy *H, int level, int op, const void *g, const void *x, void *r);

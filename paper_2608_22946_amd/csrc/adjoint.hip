@@ -1,14 +1,14 @@
 // Adjoint-state gradient of a misfit of u = Q_h v, A_h v = Q_h f, with respect
 // to the squared slowness m = 1/c^2 (Sec. 2.2 fixes that every row of A_h and
 // Q_h takes its coefficients at its own node, so d/dm_i touches row i only):
-//   transposed operators A^T, B^T (any level) and Q_h^T, gathered per output
-//   node from the rows of its 27 neighbours (tensor form, eq. iofd-pml rows);
+//   transposed operators A^T, B^T (any level; rows staged per z-plane in LDS) and
+//   Q_h^T, gathered per output node from the rows of its 27 neighbours (tensor form);
 //   the derivative of row i in m_i applied to a vector;
 //   the gradient terms conj(s_i)(d_i Q v)_i + mu_i ((d_i Q f)_i - (d_i A v)_i)
 //   accumulated in FP64, then summed onto the physical nodes (a PML node takes
 //   the velocity of its nearest physical node, Sec. 2.1).
-// These kernels are off the preconditioner's hot path: one thread per node,
-// every coefficient evaluated where it is needed.
+// Apart from A^T, these kernels run once per gradient: one thread per node, every
+// coefficient evaluated where it is needed.
 #include "helm_internal.h"
 
 namespace helm {
@@ -93,24 +93,6 @@ __device__ __forceinline__ RowW<R> row_weights(const LevelArgs<R> &L, float c) {
     return w;
 }
 
-// the same weights from per-node coefficient arrays coef[f * n + i] = (a1..a5, kappa^2)(i)
-template <typename R>
-__device__ __forceinline__ RowW<R> row_weights_pre(const R *__restrict__ coef, long long n, long long i) {
-    R a[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) a[f] = coef[f * n + i];
-    RowW<R> w;
-    w.T[0] = a[3];
-    w.T[1] = a[4] * (R)0.25;
-    w.T[2] = ((R)1 - a[3] - a[4]) * (R)0.25;
-    w.M[0] = a[0];
-    w.M[1] = a[1] * (R)(1.0 / 6);
-    w.M[2] = a[2] * (R)(1.0 / 12);
-    w.M[3] = ((R)1 - a[0] - a[1] - a[2]) * (R)0.125;
-    w.k2 = a[5];
-    return w;
-}
-
 // derivatives in m of the same weights (dk2 = d kappa^2 / dm = kappa^2 c^2) and the
 // Q_h shell weights' derivatives (b1, b2/6, b3/12, (1-b1-b2-b3)/8)
 template <typename R>
@@ -168,69 +150,107 @@ __device__ __forceinline__ bool inside(const LevelArgs<R> &L, int x, int y, int 
 
 // y = op^T x (op A, or B with SHIFT), optionally y = g - op^T x (RESID; zero on the boundary).
 // Entry (i, k) of op, i = k + delta, is row i's coefficient for the offset -delta:
-// sum_j w_j(i_j, -delta_j) T_i[nonzeros of delta off axis j] - mu kappa_i^2 M_i[|delta|_1].
-// PRE: row weights from coefficient arrays written by k_row_coefs instead of evaluated
-// (27 evaluations per output node otherwise).
-template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID, bool PRE>
-__global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
-                                                TY *__restrict__ y, const R *__restrict__ coef) {
-    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
-    if (X > L.nx || Y > L.ny) return;
-    const long long k = (long long)Zz * L.sy + (long long)Y * L.sx + X;
-    Zc<R> acc = {0, 0};
-    const bool in = inside(L, X, Y, Zz);
-    if (in) {
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int xi = X + dx, yi = Y + dy, zi = Zz + dz;
-                    if (!inside(L, xi, yi, zi)) continue;
-                    const long long i = k + dx + (long long)dy * L.sx + (long long)dz * L.sy;
-                    const RowW<R> w = PRE ? row_weights_pre(coef, (long long)(L.nz + 1) * L.sy, i)
-                                          : row_weights(L, L.c[i]);
-                    const int d[3] = {dx, dy, dz}, pos[3] = {xi, yi, zi};
-                    const R *ws[3] = {L.wx, L.wy, L.wz};
-                    Zc<R> cf = {0, 0};
+//   sum_j w_j(i_j, -delta_j) T_i[nonzeros of delta off axis j] - mu kappa_i^2 M_i[|delta|_1].
+// A block owns 64 x 4 output nodes of kTZ consecutive planes and marches in z with a
+// ring of three staged planes in LDS: every staged node holds x and the coefficient
+// functions of its own row (a1..a5, kappa^2), evaluated once per staging (about 1.5
+// times per node with the halo), so the 27 neighbour rows of an output are read from
+// LDS instead of being re-evaluated or re-fetched through the caches.
+constexpr int kTZ = 8;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHN = kHX * kHY;   // staged plane incl. halo
+
+template <typename R, typename TX>
+__device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const TX *__restrict__ x, int X0, int Y0, int z,
+                                            R (*S)[kHN]) {
+    const int tid = threadIdx.y * kTX + threadIdx.x;
+    for (int e = tid; e < kHN; e += kTX * kTY) {
+        const int c = e % kHX, r = e / kHX;
+        const int xi = X0 - 1 + c, yi = Y0 - 1 + r;
+        R v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (inside(L, xi, yi, z)) {   // rows exist at interior nodes only; x is zero elsewhere
+            const long long i = (long long)z * L.sy + (long long)yi * L.sx + xi;
+            const Zc<R> xv = load<R>(x, i);
+            const Loc<R> q = locate_at(L, L.c[i]);
+            const R *p = L.atab + q.k * 20;
+            v[0] = xv.r;
+            v[1] = xv.i;
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        const int nz = (j != 0 && dx != 0) + (j != 1 && dy != 0) + (j != 2 && dz != 0);
-                        const Zc<R> wj = axis_w(ws[j], pos[j], -d[j]);
-                        cf.r += wj.r * w.T[nz];
-                        cf.i += wj.i * w.T[nz];
-                    }
-                    const R km = w.k2 * w.M[(dx != 0) + (dy != 0) + (dz != 0)];
-                    cf.r -= km;
-                    if (SHIFT) cf.i -= L.sigma * km;
-                    const Zc<R> xv = load<R>(x, i);
-                    acc.r += cf.r * xv.r - cf.i * xv.i;
-                    acc.i += cf.r * xv.i + cf.i * xv.r;
-                }
-        acc.r *= L.inv_ell2;
-        acc.i *= L.inv_ell2;
+            for (int f = 0; f < 5; ++f) v[2 + f] = hval(p + 4 * f, q.t);
+            v[7] = q.kappa * q.kappa;
+        }
+#pragma unroll
+        for (int f = 0; f < 8; ++f) S[f][e] = v[f];
     }
-    TY o;
-    if (RESID) {
-        const Zc<R> gv = in ? load<R>(g, k) : Zc<R>{0, 0};
-        o.re = (real_of<TY>)(gv.r - acc.r);
-        o.im = (real_of<TY>)(gv.i - acc.i);
-    } else {
-        o.re = (real_of<TY>)acc.r;
-        o.im = (real_of<TY>)acc.i;
-    }
-    y[k] = o;
 }
 
-// coef[f * n + i] = (a1, .., a5, kappa^2) of row i (interior nodes; boundary rows unused)
-template <typename R>
-__global__ void __launch_bounds__(256) k_row_coefs(LevelArgs<R> L, R *__restrict__ coef) {
-    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
-    if (X > L.nx || Y > L.ny) return;
-    const long long i = (long long)Zz * L.sy + (long long)Y * L.sx + X, n = (long long)(L.nz + 1) * L.sy;
-    const Loc<R> q = locate_at(L, L.c[i]);
-    const R *p = L.atab + q.k * 20;
+template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID>
+__global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
+                                                TY *__restrict__ y) {
+    __shared__ R S[3][8][kHN];   // [ring slot][x.re, x.im, a1..a5, kappa^2][node]
+    const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * kTY, Zb = blockIdx.z * kTZ;
+    const int X = X0 + threadIdx.x, Y = Y0 + threadIdx.y;
+    const int Ze = min(Zb + kTZ, L.nz + 1);
+    const bool col = X <= L.nx && Y <= L.ny;
+    const bool inxy = X >= 1 && X <= L.nx - 1 && Y >= 1 && Y <= L.ny - 1;
+    // axis weights w_j(k_j + d, -d) of the neighbour rows, d = -1, 0, 1 (x and y fixed per thread)
+    Zc<R> Wx[3], Wy[3];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) coef[f * n + i] = hval(p + 4 * f, q.t);
-    coef[5 * n + i] = q.kappa * q.kappa;
+    for (int d = -1; d <= 1; ++d) {
+        Wx[d + 1] = inxy ? axis_w(L.wx, X + d, -d) : Zc<R>{0, 0};
+        Wy[d + 1] = inxy ? axis_w(L.wy, Y + d, -d) : Zc<R>{0, 0};
+    }
+    stage_plane(L, x, X0, Y0, Zb - 1, S[(Zb + 2) % 3]);
+    stage_plane(L, x, X0, Y0, Zb, S[Zb % 3]);
+    for (int z = Zb; z < Ze; ++z) {
+        stage_plane(L, x, X0, Y0, z + 1, S[(z + 1) % 3]);
+        __syncthreads();
+        Zc<R> acc = {0, 0};
+        const bool in = inxy && z >= 1 && z <= L.nz - 1;
+        if (in) {
+            Zc<R> Wz[3];
+#pragma unroll
+            for (int d = -1; d <= 1; ++d) Wz[d + 1] = axis_w(L.wz, z + d, -d);
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                R (*P)[kHN] = S[(z + dz + 3) % 3];
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int e = (threadIdx.y + 1 + dy) * kHX + threadIdx.x + 1 + dx;
+                        const R a1 = P[2][e], a2 = P[3][e], a3 = P[4][e], a4 = P[5][e], a5 = P[6][e], k2 = P[7][e];
+                        const R T[3] = {a4, a5 * (R)0.25, ((R)1 - a4 - a5) * (R)0.25};
+                        const int sh = (dx != 0) + (dy != 0) + (dz != 0);
+                        const R M = sh == 0 ? a1 : sh == 1 ? a2 * (R)(1.0 / 6)
+                                                 : sh == 2 ? a3 * (R)(1.0 / 12) : ((R)1 - a1 - a2 - a3) * (R)0.125;
+                        const R tx = T[(dy != 0) + (dz != 0)], ty = T[(dx != 0) + (dz != 0)],
+                                tz = T[(dx != 0) + (dy != 0)];
+                        const Zc<R> wx = Wx[dx + 1], wy = Wy[dy + 1], wz = Wz[dz + 1];
+                        Zc<R> cf = {wx.r * tx + wy.r * ty + wz.r * tz - k2 * M, wx.i * tx + wy.i * ty + wz.i * tz};
+                        if (SHIFT) cf.i -= L.sigma * k2 * M;
+                        const R xr = P[0][e], xi = P[1][e];
+                        acc.r += cf.r * xr - cf.i * xi;
+                        acc.i += cf.r * xi + cf.i * xr;
+                    }
+            }
+            acc.r *= L.inv_ell2;
+            acc.i *= L.inv_ell2;
+        }
+        if (col) {
+            const long long k = (long long)z * L.sy + (long long)Y * L.sx + X;
+            TY o;
+            if (RESID) {
+                const Zc<R> gv = in ? load<R>(g, k) : Zc<R>{0, 0};
+                o.re = (real_of<TY>)(gv.r - acc.r);
+                o.im = (real_of<TY>)(gv.i - acc.i);
+            } else {
+                o.re = (real_of<TY>)acc.r;
+                o.im = (real_of<TY>)acc.i;
+            }
+            y[k] = o;
+        }
+        __syncthreads();   // the slot of plane z - 1 is staged over next
+    }
 }
 
 // y = Q_h^T w (CONJ: of conj(w)); row i of Q_h has the shell weights of its own node
@@ -369,33 +389,16 @@ __global__ void __launch_bounds__(256) k_grad_phys(const double *__restrict__ ga
 }  // namespace
 
 template <typename R, typename TX, typename TG, typename TY>
-hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s,
-                          const R *coef) {
-    Geom gm{};
-    gm.n[0] = L.nx;
-    gm.n[1] = L.ny;
-    gm.n[2] = L.nz;
-    const dim3 grid = node_grid3(gm), blk(kTX, kTY);
-#define HELM_AT(SH, RS, PR) hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, SH, RS, PR>), grid, blk, 0, s, L, x, g, y, coef)
-    if (coef) {
-        if (shifted || g) return hipErrorInvalidValue;   // the coefficient arrays serve the plain A^T apply
-        HELM_AT(false, false, true);
-    } else if (g) {
-        if (shifted) HELM_AT(true, true, false); else HELM_AT(false, true, false);
+hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s) {
+    const dim3 grid((unsigned)((L.nx + kTX) / kTX), (unsigned)((L.ny + kTY) / kTY), (unsigned)((L.nz + kTZ) / kTZ));
+    const dim3 blk(kTX, kTY);
+#define HELM_AT(SH, RS) hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, SH, RS>), grid, blk, 0, s, L, x, g, y)
+    if (g) {
+        if (shifted) HELM_AT(true, true); else HELM_AT(false, true);
     } else {
-        if (shifted) HELM_AT(true, false, false); else HELM_AT(false, false, false);
+        if (shifted) HELM_AT(true, false); else HELM_AT(false, false);
     }
 #undef HELM_AT
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t launch_row_coefs(const LevelArgs<R> &L, R *coef, hipStream_t s) {
-    Geom gm{};
-    gm.n[0] = L.nx;
-    gm.n[1] = L.ny;
-    gm.n[2] = L.nz;
-    hipLaunchKernelGGL((k_row_coefs<R>), node_grid3(gm), dim3(kTX, kTY), 0, s, L, coef);
     return hipGetLastError();
 }
 
@@ -444,11 +447,9 @@ hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, con
 }
 
 template hipError_t launch_apply_t<float, c32, c32, c32>(const LevelArgs<float> &, int, const c32 *, const c32 *,
-                                                         c32 *, hipStream_t, const float *);
+                                                         c32 *, hipStream_t);
 template hipError_t launch_apply_t<double, c64, c64, c64>(const LevelArgs<double> &, int, const c64 *, const c64 *,
-                                                          c64 *, hipStream_t, const double *);
-template hipError_t launch_row_coefs<float>(const LevelArgs<float> &, float *, hipStream_t);
-template hipError_t launch_row_coefs<double>(const LevelArgs<double> &, double *, hipStream_t);
+                                                          c64 *, hipStream_t);
 template hipError_t launch_qapply_t<double, c32, c64>(const LevelArgs<double> &, const c32 *, bool, c64 *,
                                                       hipStream_t);
 template hipError_t launch_qapply_t<double, c64, c64>(const LevelArgs<double> &, const c64 *, bool, c64 *,

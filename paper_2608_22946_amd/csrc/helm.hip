@@ -280,9 +280,8 @@ struct Eng {
     Lane *Ln;
     hipStream_t s;
 
-    bool transposed = false;   // outer solve with A_h^T (adjoint); r64: its FP64 residual buffer,
-    c64 *r64 = nullptr;        // coef: per-node row coefficients of A_h for its working-precision applies
-    const R *coef = nullptr;
+    bool transposed = false;   // outer solve with A_h^T (adjoint); r64: its FP64 residual buffer
+    c64 *r64 = nullptr;
 
     explicit Eng(helm_hierarchy *h, int lane = 0) : H(h), Ln(&h->lane[lane]), s(h->lane[lane].s) {}
 
@@ -511,7 +510,7 @@ struct Eng {
                 HIP_TRY(precond(V[k], Zp[k]));
                 ++its;
                 if (transposed)
-                    HIP_TRY((launch_apply_t<R, T, T, T>(L(0), 0, Zp[k], (const T *)nullptr, V[k + 1], s, coef)));
+                    HIP_TRY((launch_apply_t<R, T, T, T>(L(0), 0, Zp[k], (const T *)nullptr, V[k + 1], s)));
                 else
                     HIP_TRY(stencil(0, M_APPLY, false, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
                 HIP_TRY(arnoldi(0, V, k, st, k == o.m_out - 1));
@@ -888,13 +887,11 @@ helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, v
     return worst;
 }
 
-// Gradient workspace: v (c64), the adjoint residual (c64), the FP64 per-node sums and
-// six per-node row-coefficient arrays of A_h in the working precision.
+// Gradient workspace: v (c64), the adjoint residual (c64) and the FP64 per-node sums.
 static size_t grad_ws_bytes(const helm_hierarchy *H) {
     const size_t n = (size_t)H->geom[0].nn;
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t rs = (H->prec == HELM_FP64) ? sizeof(double) : sizeof(float);
-    return 2 * up(n * sizeof(c64)) + up(n * sizeof(double)) + up(6 * n * rs);
+    return 2 * up(n * sizeof(c64)) + up(n * sizeof(double));
 }
 
 helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes) {
@@ -917,13 +914,10 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
     c64 *v64 = reinterpret_cast<c64 *>(w);
     c64 *r64 = reinterpret_cast<c64 *>(w + up(n * sizeof(c64)));
     double *gacc = reinterpret_cast<double *>(w + 2 * up(n * sizeof(c64)));
-    void *coef = w + 2 * up(n * sizeof(c64)) + up(n * sizeof(double));
     const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
     helm_status worst = HELM_OK;
     auto run = [&](auto E, auto *tag) -> helm_status {
         using TT = typename std::remove_pointer<decltype(tag)>::type;
-        using RR = typename decltype(E)::R;
-        HIP_TRY((launch_row_coefs<RR>(E.L(0), static_cast<RR *>(coef), E.s)));
         HIP_TRY((launch_fill_zero<c64>(reinterpret_cast<c64 *>(gacc), n / 2, E.s)));   // n doubles
         if (n & 1) HIP_TRY(hipMemsetAsync(gacc + n - 1, 0, sizeof(double), E.s));
         for (int r = 0; r < nrhs; ++r) {
@@ -938,7 +932,6 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
             HIP_TRY((launch_qapply_t<double, TT, c64>(H->Ld[0], sr, true, E.Ln->b64, E.s)));
             E.transposed = true;
             E.r64 = r64;
-            E.coef = static_cast<const RR *>(coef);
             st = E.solve_b64(tol, iters + 2 * r + 1, relres + 2 * r + 1);
             E.transposed = false;
             if (st < 0) return st;
@@ -988,24 +981,6 @@ helm_status helm_apply(helm_hierarchy *H, int level, int op, const void *x, void
         if (op == HELM_OP_Q)
             return launch_qapply<typename T::R, TT, TT>(E.L(0), (const TT *)x, (TT *)y, E.s);
         return launch_diag<typename T::R, TT>(E.L(level), op == HELM_OP_DIAG_B, (const TT *)x, (TT *)y, E.s);
-    });
-}
-
-helm_status helm_row_coefs(helm_hierarchy *H, void *coef) {
-    if (!H || !coef) return fail(H, HELM_EINVAL, "invalid row-coefficient arguments");
-    return dispatch(H, [&](auto E) -> hipError_t {
-        using RR = typename decltype(E)::R;
-        return launch_row_coefs<RR>(E.L(0), static_cast<RR *>(coef), E.s);
-    });
-}
-
-helm_status helm_apply_t_rows(helm_hierarchy *H, const void *coef, const void *x, void *y) {
-    if (!H || !coef || !x || !y || x == y) return fail(H, HELM_EINVAL, "invalid transposed-apply arguments");
-    return dispatch(H, [&](auto E) -> hipError_t {
-        using RR = typename decltype(E)::R;
-        using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
-        return launch_apply_t<RR, TT, TT, TT>(E.L(0), 0, (const TT *)x, (const TT *)nullptr, (TT *)y, E.s,
-                                              static_cast<const RR *>(coef));
     });
 }
 

@@ -181,10 +181,7 @@ hipError_t launch_dinv(const LevelArgs<R> &L, int shifted, R *out, hipStream_t s
 // (which 0: A, 1: Q_h), the per-node gradient terms accumulated into gacc, and their sum
 // onto the physical nodes.
 template <typename R, typename TX, typename TG, typename TY>
-hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s,
-                          const R *coef = nullptr);   // coef: per-node (a1..a5, kappa^2) arrays, plain A^T only
-template <typename R>
-hipError_t launch_row_coefs(const LevelArgs<R> &L, R *coef, hipStream_t s);   // coef[f * nn + i], 6 arrays
+hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s);
 template <typename R, typename TI, typename TO>
 hipError_t launch_qapply_t(const LevelArgs<R> &L, const TI *w, bool conj_in, TO *y, hipStream_t s);
 template <typename R, typename T>

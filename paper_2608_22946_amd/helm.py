@@ -36,7 +36,7 @@ class HelmOptions(ctypes.Structure):
 
 
 EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_grad",
-            "helm_grad_workspace_size", "helm_row_coefs", "helm_apply_t_rows", "helm_destroy",
+            "helm_grad_workspace_size", "helm_destroy",
             "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_residual_restrict", "helm_jacobi",
             "helm_restrict",
             "helm_prolong_add", "helm_bottom", "helm_vcycle", "helm_coarse_solve", "helm_smooth", "helm_precond",
@@ -59,8 +59,6 @@ def lib():
         L.helm_solve.argtypes = [P, P, I, D, P, P, P]
         L.helm_grad.argtypes = [P, P, P, I, D, P, P, _c_size_t, P, P]
         L.helm_grad_workspace_size.argtypes = [P, ctypes.POINTER(_c_size_t)]
-        L.helm_row_coefs.argtypes = [P, P]
-        L.helm_apply_t_rows.argtypes = [P, P, P, P]
         L.helm_destroy.argtypes = [P]
         L.helm_destroy.restype = None
         L.helm_last_error.argtypes = [P]
@@ -263,19 +261,6 @@ class Hierarchy:
         _check(lib().helm_vec_orthonormalize(self._h, level, k, arr, self._vec(w, level), out.ctypes.data), self._h)
         c = out[0::2] + 1j * out[1::2]
         return c[:k], c[k].real
-
-    def row_coefs(self):
-        """Per-node row coefficients of A_h (6 arrays over the fine nodes, working precision)."""
-        rdt = torch.float64 if self.precision == "fp64" else torch.float32
-        c = torch.empty((6,) + self.shape(0), dtype=rdt, device=self.device)
-        _check(lib().helm_row_coefs(self._h, _ptr(c)), self._h)
-        return c
-
-    def apply_t_rows(self, coef, x, out=None):
-        """A_h^T x from row_coefs() (the adjoint solve's kernel)."""
-        y = self.empty(0) if out is None else out
-        _check(lib().helm_apply_t_rows(self._h, _ptr(coef), self._vec(x, 0), self._vec(y, 0)), self._h)
-        return y
 
     def grad(self, f, adj_src, tol):
         """dJ/dm (m = 1/c^2) at the physical nodes for sources f and adjoint sources s

@@ -461,15 +461,6 @@ def test_apply_transposed(pair, level, op):
     assert err <= pair.tol(1e-12, 1e-6), err
 
 
-def test_apply_transposed_from_row_coefficients(pair):
-    """The adjoint solve's A_h^T (row coefficients stored per node) against the checker."""
-    x = pair.rand(0, 321)
-    coef = pair.g.row_coefs()
-    y = to_np(pair.g.apply_t_rows(coef, pair.dev(x)))
-    err = rel(y, pair.o.apply_t(0, 0, x.astype(complex)))
-    assert err <= pair.tol(1e-12, 1e-6), err
-
-
 @pytest.mark.parametrize("op", [8, 9])
 def test_apply_row_derivative(pair, op):
     """y_i = (d_i A_h x)_i and (d_i Q_h x)_i, m = 1/c^2, against the checker."""
