@@ -1,7 +1,7 @@
 // Adjoint-state gradient of a misfit of u = Q_h v, A_h v = Q_h f, with respect
 // to the squared slowness m = 1/c^2 (Sec. 2.2 fixes that every row of A_h and
 // Q_h takes its coefficients at its own node, so d/dm_i touches row i only):
-//   transposed operators A^T, B^T (any level; rows staged per z-plane in LDS) and
+//   transposed operators A^T, B^T (any level; rows staged plane by plane in LDS) and
 //   Q_h^T, gathered per output node from the rows of its 27 neighbours (tensor form);
 //   the derivative of row i in m_i applied to a vector;
 //   the gradient terms conj(s_i)(d_i Q v)_i + mu_i ((d_i Q f)_i - (d_i A v)_i)
@@ -151,12 +151,13 @@ __device__ __forceinline__ bool inside(const LevelArgs<R> &L, int x, int y, int 
 // y = op^T x (op A, or B with SHIFT), optionally y = g - op^T x (RESID; zero on the boundary).
 // Entry (i, k) of op, i = k + delta, is row i's coefficient for the offset -delta:
 //   sum_j w_j(i_j, -delta_j) T_i[nonzeros of delta off axis j] - mu kappa_i^2 M_i[|delta|_1].
-// A block owns 64 x 4 output nodes of kTZ consecutive planes and marches in z with a
-// ring of three staged planes in LDS: every staged node holds x and the coefficient
-// functions of its own row (a1..a5, kappa^2), evaluated once per staging (about 1.5
-// times per node with the halo), so the 27 neighbour rows of an output are read from
-// LDS instead of being re-evaluated or re-fetched through the caches.
-constexpr int kTZ = 8;
+// A block owns 64 x 4 output nodes of kTZ consecutive planes and marches in z, staging one
+// plane at a time in LDS: every staged node holds x and the coefficient functions of its
+// own row (a1..a5, kappa^2), evaluated once per staging (about 1.5 times per node with the
+// halo).  A staged plane p holds the neighbour rows of the outputs in planes p - 1, p and
+// p + 1, so each thread reads its 9 in-plane neighbours once and adds their terms to three
+// running sums; the sum of plane p - 1 is complete and stored after plane p.
+constexpr int kTZ = 16;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHN = kHX * kHY;   // staged plane incl. halo
 
 template <typename R, typename TX>
@@ -186,7 +187,7 @@ __device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const TX *__r
 template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID>
 __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
                                                 TY *__restrict__ y) {
-    __shared__ R S[3][8][kHN];   // [ring slot][x.re, x.im, a1..a5, kappa^2][node]
+    __shared__ R S[8][kHN];   // [x.re, x.im, a1..a5, kappa^2][node] of the staged plane
     const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * kTY, Zb = blockIdx.z * kTZ;
     const int X = X0 + threadIdx.x, Y = Y0 + threadIdx.y;
     const int Ze = min(Zb + kTZ, L.nz + 1);
@@ -199,57 +200,61 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
         Wx[d + 1] = inxy ? axis_w(L.wx, X + d, -d) : Zc<R>{0, 0};
         Wy[d + 1] = inxy ? axis_w(L.wy, Y + d, -d) : Zc<R>{0, 0};
     }
-    stage_plane(L, x, X0, Y0, Zb - 1, S[(Zb + 2) % 3]);
-    stage_plane(L, x, X0, Y0, Zb, S[Zb % 3]);
-    for (int z = Zb; z < Ze; ++z) {
-        stage_plane(L, x, X0, Y0, z + 1, S[(z + 1) % 3]);
+    // acc[0], acc[1], acc[2]: running sums of the outputs in planes p - 1, p, p + 1
+    Zc<R> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int p = Zb - 1; p <= Ze; ++p) {
+        stage_plane(L, x, X0, Y0, p, S);
         __syncthreads();
-        Zc<R> acc = {0, 0};
-        const bool in = inxy && z >= 1 && z <= L.nz - 1;
-        if (in) {
+        if (inxy && p >= 1 && p <= L.nz - 1) {   // only interior planes hold rows
+            // z weights of row plane p seen from output plane p - dz: w_z(p, -dz)
             Zc<R> Wz[3];
 #pragma unroll
-            for (int d = -1; d <= 1; ++d) Wz[d + 1] = axis_w(L.wz, z + d, -d);
+            for (int dz = -1; dz <= 1; ++dz) Wz[dz + 1] = axis_w(L.wz, p, -dz);
 #pragma unroll
-            for (int dz = -1; dz <= 1; ++dz) {
-                R (*P)[kHN] = S[(z + dz + 3) % 3];
+            for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-                for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int e = (threadIdx.y + 1 + dy) * kHX + threadIdx.x + 1 + dx;
+                    const R a1 = S[2][e], a2 = S[3][e], a3 = S[4][e], a4 = S[5][e], a5 = S[6][e], k2 = S[7][e];
+                    const R xr = S[0][e], xi = S[1][e];
+                    const R T[3] = {a4, a5 * (R)0.25, ((R)1 - a4 - a5) * (R)0.25};
+                    const R Ms[4] = {a1, a2 * (R)(1.0 / 6), a3 * (R)(1.0 / 12), ((R)1 - a1 - a2 - a3) * (R)0.125};
+                    const int sxy = (dx != 0) + (dy != 0);
+                    const Zc<R> wx = Wx[dx + 1], wy = Wy[dy + 1];
 #pragma unroll
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        const int e = (threadIdx.y + 1 + dy) * kHX + threadIdx.x + 1 + dx;
-                        const R a1 = P[2][e], a2 = P[3][e], a3 = P[4][e], a4 = P[5][e], a5 = P[6][e], k2 = P[7][e];
-                        const R T[3] = {a4, a5 * (R)0.25, ((R)1 - a4 - a5) * (R)0.25};
-                        const int sh = (dx != 0) + (dy != 0) + (dz != 0);
-                        const R M = sh == 0 ? a1 : sh == 1 ? a2 * (R)(1.0 / 6)
-                                                 : sh == 2 ? a3 * (R)(1.0 / 12) : ((R)1 - a1 - a2 - a3) * (R)0.125;
-                        const R tx = T[(dy != 0) + (dz != 0)], ty = T[(dx != 0) + (dz != 0)],
-                                tz = T[(dx != 0) + (dy != 0)];
-                        const Zc<R> wx = Wx[dx + 1], wy = Wy[dy + 1], wz = Wz[dz + 1];
-                        Zc<R> cf = {wx.r * tx + wy.r * ty + wz.r * tz - k2 * M, wx.i * tx + wy.i * ty + wz.i * tz};
-                        if (SHIFT) cf.i -= L.sigma * k2 * M;
-                        const R xr = P[0][e], xi = P[1][e];
-                        acc.r += cf.r * xr - cf.i * xi;
-                        acc.i += cf.r * xi + cf.i * xr;
+                    for (int dz = -1; dz <= 1; ++dz) {   // contribution to output plane p - dz
+                        const int nzz = dz != 0;
+                        const R tx = T[(dy != 0) + nzz], ty = T[(dx != 0) + nzz], tz = T[sxy];
+                        const R km = k2 * Ms[sxy + nzz];
+                        const Zc<R> wz = Wz[dz + 1];
+                        Zc<R> cf = {wx.r * tx + wy.r * ty + wz.r * tz - km, wx.i * tx + wy.i * ty + wz.i * tz};
+                        if (SHIFT) cf.i -= L.sigma * km;
+                        Zc<R> &a = acc[1 - dz];
+                        a.r += cf.r * xr - cf.i * xi;
+                        a.i += cf.r * xi + cf.i * xr;
                     }
-            }
-            acc.r *= L.inv_ell2;
-            acc.i *= L.inv_ell2;
+                }
         }
-        if (col) {
+        const int z = p - 1;   // all three neighbour planes of output plane p - 1 are in
+        if (col && z >= Zb && z < Ze) {
+            const bool in = inxy && z >= 1 && z <= L.nz - 1;
             const long long k = (long long)z * L.sy + (long long)Y * L.sx + X;
+            const Zc<R> v = in ? Zc<R>{acc[0].r * L.inv_ell2, acc[0].i * L.inv_ell2} : Zc<R>{0, 0};
             TY o;
             if (RESID) {
                 const Zc<R> gv = in ? load<R>(g, k) : Zc<R>{0, 0};
-                o.re = (real_of<TY>)(gv.r - acc.r);
-                o.im = (real_of<TY>)(gv.i - acc.i);
+                o.re = (real_of<TY>)(gv.r - v.r);
+                o.im = (real_of<TY>)(gv.i - v.i);
             } else {
-                o.re = (real_of<TY>)acc.r;
-                o.im = (real_of<TY>)acc.i;
+                o.re = (real_of<TY>)v.r;
+                o.im = (real_of<TY>)v.i;
             }
             y[k] = o;
         }
-        __syncthreads();   // the slot of plane z - 1 is staged over next
+        acc[0] = acc[1];
+        acc[1] = acc[2];
+        acc[2] = Zc<R>{0, 0};
+        __syncthreads();   // the staged plane is overwritten next
     }
 }
 
