@@ -371,6 +371,32 @@ __global__ void __launch_bounds__(256) k_grad_node(LevelArgs<double> L, const c6
     gacc[k] += (si.r * dQv.r + si.i * dQv.i) + (mi.r * tr - mi.i * ti);
 }
 
+// out = in * prod_j (1/xi_j) (inverse = 0) or in / prod_j (1/xi_j) (inverse = 1): the
+// diagonal Xi = prod_j xi_j(i_j) of the PML node factors, which relates A^T to A (in one
+// dimension the stretched second difference L = Xi^-1 K with K symmetric, so L^T = Xi L Xi^-1)
+template <typename T>
+__global__ void __launch_bounds__(256) k_xi_scale(Geom F, const c64 *__restrict__ xin, const T *in, T *out,
+                                                 int inverse) {
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
+    if (X > F.n[0] || Y > F.n[1]) return;
+    const long long i = (long long)Zz * F.sy + (long long)Y * F.sx + X;
+    const c64 a = xin[X], b = xin[F.n[0] + 1 + Y], c = xin[F.n[0] + F.n[1] + 2 + Zz];
+    double fr = a.re * b.re - a.im * b.im, fi = a.re * b.im + a.im * b.re;
+    const double gr = fr * c.re - fi * c.im, gi = fr * c.im + fi * c.re;
+    fr = gr;
+    fi = gi;
+    if (inverse) {
+        const double d = fr * fr + fi * fi;
+        fr = fr / d;
+        fi = -fi / d;
+    }
+    const Zc<double> v = load<double>(in, i);
+    T o;
+    o.re = (real_of<T>)(v.r * fr - v.i * fi);
+    o.im = (real_of<T>)(v.r * fi + v.i * fr);
+    out[i] = o;
+}
+
 // out_p = sum of gacc over the total-grid nodes whose nearest physical node is p
 __global__ void __launch_bounds__(256) k_grad_phys(const double *__restrict__ gacc, Geom F, int n_pml, int nxp,
                                                   int nyp, int nzp, float *__restrict__ out) {
@@ -444,6 +470,12 @@ hipError_t launch_grad_node(const LevelArgs<double> &L, const c64 *v, const c64 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_xi_scale(const Geom &F, const c64 *xin, const T *in, T *out, bool inverse, hipStream_t s) {
+    hipLaunchKernelGGL((k_xi_scale<T>), node_grid3(F), dim3(kTX, kTY), 0, s, F, xin, in, out, inverse ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, const int nphys[3], float *out,
                             hipStream_t s) {
     const dim3 grid((unsigned)((nphys[0] + kTX) / kTX), (unsigned)((nphys[1] + kTY) / kTY), (unsigned)(nphys[2] + 1));
@@ -462,6 +494,8 @@ template hipError_t launch_qapply_t<double, c64, c64>(const LevelArgs<double> &,
 template hipError_t launch_qapply_t<float, c32, c32>(const LevelArgs<float> &, const c32 *, bool, c32 *, hipStream_t);
 template hipError_t launch_apply_dm<float, c32>(const LevelArgs<float> &, int, const c32 *, c32 *, hipStream_t);
 template hipError_t launch_apply_dm<double, c64>(const LevelArgs<double> &, int, const c64 *, c64 *, hipStream_t);
+template hipError_t launch_xi_scale<c32>(const Geom &, const c64 *, const c32 *, c32 *, bool, hipStream_t);
+template hipError_t launch_xi_scale<c64>(const Geom &, const c64 *, const c64 *, c64 *, bool, hipStream_t);
 template hipError_t launch_grad_node<c32>(const LevelArgs<double> &, const c64 *, const c64 *, const c32 *,
                                           const c32 *, double *, hipStream_t);
 template hipError_t launch_grad_node<c64>(const LevelArgs<double> &, const c64 *, const c64 *, const c64 *,

@@ -280,8 +280,10 @@ struct Eng {
     Lane *Ln;
     hipStream_t s;
 
-    bool transposed = false;   // outer solve with A_h^T (adjoint); r64: its FP64 residual buffer
-    c64 *r64 = nullptr;
+    bool transposed = false;   // outer solve with A_h^T (adjoint); r64: its FP64 residual buffer;
+    c64 *r64 = nullptr;        // xin, u: PML node factors and a vector for the preconditioner Xi M(Xi^-1 .)
+    const c64 *xin = nullptr;
+    T *u_t = nullptr;
 
     explicit Eng(helm_hierarchy *h, int lane = 0) : H(h), Ln(&h->lane[lane]), s(h->lane[lane].s) {}
 
@@ -507,7 +509,15 @@ struct Eng {
             }
             int kk = 0;   // V[0] = r stays unnormalised (the state holds 1/beta)
             for (int k = 0; k < o.m_out; ++k) {
-                HIP_TRY(precond(V[k], Zp[k]));
+                if (transposed && xin) {
+                    // A_h^T is close to Xi A_h Xi^-1 (the PML row factors move to the columns), so
+                    // Xi M_h^-1 Xi^-1 approximates its inverse
+                    HIP_TRY(launch_xi_scale<T>(H->geom[0], xin, V[k], u_t, false, s));
+                    HIP_TRY(precond(u_t, Zp[k]));
+                    HIP_TRY(launch_xi_scale<T>(H->geom[0], xin, Zp[k], Zp[k], true, s));
+                } else {
+                    HIP_TRY(precond(V[k], Zp[k]));
+                }
                 ++its;
                 if (transposed)
                     HIP_TRY((launch_apply_t<R, T, T, T>(L(0), 0, Zp[k], (const T *)nullptr, V[k + 1], s)));
@@ -887,11 +897,15 @@ helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, v
     return worst;
 }
 
-// Gradient workspace: v (c64), the adjoint residual (c64) and the FP64 per-node sums.
+// Gradient workspace: v (c64), the adjoint residual (c64), the FP64 per-node sums, one
+// working-precision vector and the per-axis PML node factors 1/xi (c64).
 static size_t grad_ws_bytes(const helm_hierarchy *H) {
     const size_t n = (size_t)H->geom[0].nn;
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return 2 * up(n * sizeof(c64)) + up(n * sizeof(double));
+    const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
+    const Geom &g = H->geom[0];
+    return 2 * up(n * sizeof(c64)) + up(n * sizeof(double)) + up(n * es) +
+           up((size_t)(g.n[0] + g.n[1] + g.n[2] + 3) * sizeof(c64));
 }
 
 helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes) {
@@ -915,6 +929,28 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
     c64 *r64 = reinterpret_cast<c64 *>(w + up(n * sizeof(c64)));
     double *gacc = reinterpret_cast<double *>(w + 2 * up(n * sizeof(c64)));
     const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
+    void *u_t = w + 2 * up(n * sizeof(c64)) + up(n * sizeof(double));
+    c64 *xin = reinterpret_cast<c64 *>(w + 2 * up(n * sizeof(c64)) + up(n * sizeof(double)) + up(n * es));
+    {   // 1/xi_j at the fine nodes of each axis (eq. pml-profile), x then y then z
+        const Geom &g = H->geom[0];
+        const double Lpml = H->n_pml * H->h;
+        std::vector<c64> hx;
+        for (int a = 0; a < 3; ++a) {
+            const double L = g.n[a] * H->h;
+            for (int j = 0; j <= g.n[a]; ++j) {
+                const double xj = j * H->h;
+                double gam = 0.0;
+                if (Lpml > 0) {
+                    const double d = std::min(Lpml, std::max(0.0, std::max(Lpml - xj, xj - (L - Lpml))));
+                    gam = H->opt.gamma_max * (1.0 - std::cos(M_PI * d / (2.0 * Lpml)));
+                }
+                const double den = 1.0 + gam * gam;
+                hx.push_back(c64{1.0 / den, -gam / den});
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(xin, hx.data(), hx.size() * sizeof(c64), hipMemcpyHostToDevice, H->s));
+        HIP_TRY(hipStreamSynchronize(H->s));
+    }
     helm_status worst = HELM_OK;
     auto run = [&](auto E, auto *tag) -> helm_status {
         using TT = typename std::remove_pointer<decltype(tag)>::type;
@@ -932,6 +968,8 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
             HIP_TRY((launch_qapply_t<double, TT, c64>(H->Ld[0], sr, true, E.Ln->b64, E.s)));
             E.transposed = true;
             E.r64 = r64;
+            E.xin = xin;
+            E.u_t = static_cast<TT *>(u_t);
             st = E.solve_b64(tol, iters + 2 * r + 1, relres + 2 * r + 1);
             E.transposed = false;
             if (st < 0) return st;
