@@ -371,29 +371,27 @@ __global__ void __launch_bounds__(256) k_grad_node(LevelArgs<double> L, const c6
     gacc[k] += (si.r * dQv.r + si.i * dQv.i) + (mi.r * tr - mi.i * ti);
 }
 
-// out = in * prod_j (1/xi_j) (inverse = 0) or in / prod_j (1/xi_j) (inverse = 1): the
-// diagonal Xi = prod_j xi_j(i_j) of the PML node factors, which relates A^T to A (in one
-// dimension the stretched second difference L = Xi^-1 K with K symmetric, so L^T = Xi L Xi^-1)
-template <typename T>
-__global__ void __launch_bounds__(256) k_xi_scale(Geom F, const c64 *__restrict__ xin, const T *in, T *out,
+// out = in * prod_j f_j(i_j) with f the per-axis node factors 1/xi_j (inverse = 0) or xi_j
+// (inverse = 1): the diagonal Xi = prod_j xi_j(i_j) of the PML node factors, which relates
+// A^T to A (in one dimension the stretched second difference L = Xi^-1 K with K symmetric,
+// so L^T = Xi L Xi^-1).  Xi is 1 off the PML: with in == out those nodes are not touched.
+template <typename R, typename T>
+__global__ void __launch_bounds__(256) k_xi_scale(Geom F, const c64 *__restrict__ fac, const T *in, T *out,
                                                  int inverse) {
     const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zz = blockIdx.z;
     if (X > F.n[0] || Y > F.n[1]) return;
     const long long i = (long long)Zz * F.sy + (long long)Y * F.sx + X;
-    const c64 a = xin[X], b = xin[F.n[0] + 1 + Y], c = xin[F.n[0] + F.n[1] + 2 + Zz];
-    double fr = a.re * b.re - a.im * b.im, fi = a.re * b.im + a.im * b.re;
-    const double gr = fr * c.re - fi * c.im, gi = fr * c.im + fi * c.re;
-    fr = gr;
-    fi = gi;
-    if (inverse) {
-        const double d = fr * fr + fi * fi;
-        fr = fr / d;
-        fi = -fi / d;
-    }
-    const Zc<double> v = load<double>(in, i);
+    const int plane = (F.n[0] + F.n[1] + F.n[2] + 3) * inverse;   // factors: 1/xi, then xi
+    const c64 a = fac[plane + X], b = fac[plane + F.n[0] + 1 + Y], c = fac[plane + F.n[0] + F.n[1] + 2 + Zz];
+    const bool one = a.im == 0.0 && b.im == 0.0 && c.im == 0.0;   // gamma = 0 on all three axes
+    if (one && in == out) return;
+    const R ar = (R)a.re, ai = (R)a.im, br = (R)b.re, bi = (R)b.im, cr = (R)c.re, ci = (R)c.im;
+    const R fr0 = ar * br - ai * bi, fi0 = ar * bi + ai * br;
+    const R fr = fr0 * cr - fi0 * ci, fi = fr0 * ci + fi0 * cr;
+    const T v = in[i];
     T o;
-    o.re = (real_of<T>)(v.r * fr - v.i * fi);
-    o.im = (real_of<T>)(v.r * fi + v.i * fr);
+    o.re = (real_of<T>)((R)v.re * fr - (R)v.im * fi);
+    o.im = (real_of<T>)((R)v.re * fi + (R)v.im * fr);
     out[i] = o;
 }
 
@@ -471,8 +469,9 @@ hipError_t launch_grad_node(const LevelArgs<double> &L, const c64 *v, const c64 
 }
 
 template <typename T>
-hipError_t launch_xi_scale(const Geom &F, const c64 *xin, const T *in, T *out, bool inverse, hipStream_t s) {
-    hipLaunchKernelGGL((k_xi_scale<T>), node_grid3(F), dim3(kTX, kTY), 0, s, F, xin, in, out, inverse ? 1 : 0);
+hipError_t launch_xi_scale(const Geom &F, const c64 *fac, const T *in, T *out, bool inverse, hipStream_t s) {
+    using R = real_of<T>;
+    hipLaunchKernelGGL((k_xi_scale<R, T>), node_grid3(F), dim3(kTX, kTY), 0, s, F, fac, in, out, inverse ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -282,7 +282,7 @@ struct Eng {
 
     bool transposed = false;   // outer solve with A_h^T (adjoint); r64: its FP64 residual buffer;
     c64 *r64 = nullptr;        // xin, u: PML node factors and a vector for the preconditioner Xi M(Xi^-1 .)
-    const c64 *xin = nullptr;
+    const c64 *xin = nullptr;   // 1/xi_j then xi_j per axis (launch_xi_scale)
     T *u_t = nullptr;
 
     explicit Eng(helm_hierarchy *h, int lane = 0) : H(h), Ln(&h->lane[lane]), s(h->lane[lane].s) {}
@@ -924,7 +924,7 @@ static size_t grad_ws_bytes(const helm_hierarchy *H) {
     const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
     const Geom &g = H->geom[0];
     return 2 * up(n * sizeof(c64)) + up(n * sizeof(double)) + up(n * es) +
-           up((size_t)(g.n[0] + g.n[1] + g.n[2] + 3) * sizeof(c64));
+           up(2 * (size_t)(g.n[0] + g.n[1] + g.n[2] + 3) * sizeof(c64));
 }
 
 helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes) {
@@ -950,10 +950,11 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
     const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
     void *u_t = w + 2 * up(n * sizeof(c64)) + up(n * sizeof(double));
     c64 *xin = reinterpret_cast<c64 *>(w + 2 * up(n * sizeof(c64)) + up(n * sizeof(double)) + up(n * es));
-    {   // 1/xi_j at the fine nodes of each axis (eq. pml-profile), x then y then z
+    {   // 1/xi_j, then xi_j, at the fine nodes of each axis (eq. pml-profile), x then y then z
         const Geom &g = H->geom[0];
         const double Lpml = H->n_pml * H->h;
         std::vector<c64> hx;
+        for (int q = 0; q < 2; ++q)
         for (int a = 0; a < 3; ++a) {
             const double L = g.n[a] * H->h;
             for (int j = 0; j <= g.n[a]; ++j) {
@@ -964,7 +965,7 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
                     gam = H->opt.gamma_max * (1.0 - std::cos(M_PI * d / (2.0 * Lpml)));
                 }
                 const double den = 1.0 + gam * gam;
-                hx.push_back(c64{1.0 / den, -gam / den});
+                hx.push_back(q == 0 ? c64{1.0 / den, -gam / den} : c64{1.0, gam});
             }
         }
         HIP_TRY(hipMemcpyAsync(xin, hx.data(), hx.size() * sizeof(c64), hipMemcpyHostToDevice, H->s));

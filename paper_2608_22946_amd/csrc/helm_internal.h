@@ -189,10 +189,11 @@ hipError_t launch_apply_dm(const LevelArgs<R> &L, int which, const T *x, T *y, h
 template <typename TS>
 hipError_t launch_grad_node(const LevelArgs<double> &L, const c64 *v, const c64 *mu, const TS *s_, const TS *f,
                             double *gacc, hipStream_t s);
-// out = in * Xi^-1 (inverse false) or in * Xi (inverse true), Xi = prod_j xi_j(i_j), xin = the per-axis
-// node factors 1/xi_j concatenated (x, y, z; n_j + 1 each); in may equal out
+// out = in * Xi^-1 (inverse false) or in * Xi (inverse true), Xi = prod_j xi_j(i_j); fac = the per-axis
+// node factors 1/xi_j concatenated (x, y, z; n_j + 1 each), followed by xi_j in the same layout;
+// in may equal out (then nodes off the PML are not touched)
 template <typename T>
-hipError_t launch_xi_scale(const Geom &F, const c64 *xin, const T *in, T *out, bool inverse, hipStream_t s);
+hipError_t launch_xi_scale(const Geom &F, const c64 *fac, const T *in, T *out, bool inverse, hipStream_t s);
 hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, const int nphys[3], float *out,
                             hipStream_t s);
 
