@@ -152,42 +152,51 @@ __device__ __forceinline__ bool inside(const LevelArgs<R> &L, int x, int y, int 
 // Entry (i, k) of op, i = k + delta, is row i's coefficient for the offset -delta:
 //   sum_j w_j(i_j, -delta_j) T_i[nonzeros of delta off axis j] - mu kappa_i^2 M_i[|delta|_1].
 // A block owns 64 x 4 output nodes of kTZ consecutive planes and marches in z, staging one
-// plane at a time in LDS: every staged node holds x and the coefficient functions of its
-// own row (a1..a5, kappa^2), evaluated once per staging (about 1.5 times per node with the
-// halo).  A staged plane p holds the neighbour rows of the outputs in planes p - 1, p and
-// p + 1, so each thread reads its 9 in-plane neighbours once and adds their terms to three
-// running sums; the sum of plane p - 1 is complete and stored after plane p.
+// plane at a time in LDS: every staged node holds x and the weights of its own row, from the
+// coefficient functions evaluated once per staging (about 1.7 times per node with the halos):
+// T = (a4, a5/4, (1-a4-a5)/4) and kappa^2 M = kappa^2 (a1, a2/6, a3/12, (1-a1-a2-a3)/8).
+// A staged plane p holds the neighbour rows of the outputs in planes p - 1, p and p + 1, so
+// each thread reads its 9 in-plane neighbours once and adds their terms to three running
+// sums; the sum of plane p - 1 is complete and stored after plane p.
 constexpr int kTZ = 16;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHN = kHX * kHY;   // staged plane incl. halo
 
 template <typename R, typename TX>
 __device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const TX *__restrict__ x, int X0, int Y0, int z,
-                                            R (*S)[kHN]) {
+                                            R (*S)[kHN]) {   // S: 9 arrays of kHN
     const int tid = threadIdx.y * kTX + threadIdx.x;
     for (int e = tid; e < kHN; e += kTX * kTY) {
         const int c = e % kHX, r = e / kHX;
         const int xi = X0 - 1 + c, yi = Y0 - 1 + r;
-        R v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        R v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (inside(L, xi, yi, z)) {   // rows exist at interior nodes only; x is zero elsewhere
             const long long i = (long long)z * L.sy + (long long)yi * L.sx + xi;
             const Zc<R> xv = load<R>(x, i);
             const Loc<R> q = locate_at(L, L.c[i]);
             const R *p = L.atab + q.k * 20;
+            R a[5];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) a[f] = hval(p + 4 * f, q.t);
+            const R k2 = q.kappa * q.kappa;
             v[0] = xv.r;
             v[1] = xv.i;
-#pragma unroll
-            for (int f = 0; f < 5; ++f) v[2 + f] = hval(p + 4 * f, q.t);
-            v[7] = q.kappa * q.kappa;
+            v[2] = a[3];
+            v[3] = a[4] * (R)0.25;
+            v[4] = ((R)1 - a[3] - a[4]) * (R)0.25;
+            v[5] = k2 * a[0];
+            v[6] = k2 * a[1] * (R)(1.0 / 6);
+            v[7] = k2 * a[2] * (R)(1.0 / 12);
+            v[8] = k2 * ((R)1 - a[0] - a[1] - a[2]) * (R)0.125;
         }
 #pragma unroll
-        for (int f = 0; f < 8; ++f) S[f][e] = v[f];
+        for (int f = 0; f < 9; ++f) S[f][e] = v[f];
     }
 }
 
 template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID>
 __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
                                                 TY *__restrict__ y) {
-    __shared__ R S[8][kHN];   // [x.re, x.im, a1..a5, kappa^2][node] of the staged plane
+    __shared__ R S[9][kHN];   // [x.re, x.im, T0..T2, kappa^2 M0..M3][node] of the staged plane
     const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * kTY, Zb = blockIdx.z * kTZ;
     const int X = X0 + threadIdx.x, Y = Y0 + threadIdx.y;
     const int Ze = min(Zb + kTZ, L.nz + 1);
@@ -215,17 +224,16 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int e = (threadIdx.y + 1 + dy) * kHX + threadIdx.x + 1 + dx;
-                    const R a1 = S[2][e], a2 = S[3][e], a3 = S[4][e], a4 = S[5][e], a5 = S[6][e], k2 = S[7][e];
                     const R xr = S[0][e], xi = S[1][e];
-                    const R T[3] = {a4, a5 * (R)0.25, ((R)1 - a4 - a5) * (R)0.25};
-                    const R Ms[4] = {a1, a2 * (R)(1.0 / 6), a3 * (R)(1.0 / 12), ((R)1 - a1 - a2 - a3) * (R)0.125};
+                    const R T[3] = {S[2][e], S[3][e], S[4][e]};
+                    const R KM[4] = {S[5][e], S[6][e], S[7][e], S[8][e]};
                     const int sxy = (dx != 0) + (dy != 0);
                     const Zc<R> wx = Wx[dx + 1], wy = Wy[dy + 1];
 #pragma unroll
                     for (int dz = -1; dz <= 1; ++dz) {   // contribution to output plane p - dz
                         const int nzz = dz != 0;
                         const R tx = T[(dy != 0) + nzz], ty = T[(dx != 0) + nzz], tz = T[sxy];
-                        const R km = k2 * Ms[sxy + nzz];
+                        const R km = KM[sxy + nzz];
                         const Zc<R> wz = Wz[dz + 1];
                         Zc<R> cf = {wx.r * tx + wy.r * ty + wz.r * tz - km, wx.i * tx + wy.i * ty + wz.i * tz};
                         if (SHIFT) cf.i -= L.sigma * km;

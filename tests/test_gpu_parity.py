@@ -503,3 +503,28 @@ def test_c2_transpose_identity(c2):
         rhs = torch.sum(x.to(torch.complex128) * aty).item()
         scale = (torch.linalg.vector_norm(ax) * torch.linalg.vector_norm(y.to(torch.complex128))).item()
         assert abs(lhs - rhs) <= 1e-5 * scale, (level, lhs, rhs)
+
+
+def test_grad_edge_cases():
+    """A zero adjoint source gives a zero gradient (the adjoint solve returns at once);
+    a workspace below helm_grad_workspace_size is rejected before any device work."""
+    import ctypes
+    from paper_2608_22946_amd import helm
+    vel = grf_velocity(16, 12, 12, seed=43, corr_len=4.0)
+    p = Pair(vel, 2, "fp32")
+    nx, ny, nz = p.g.dims(0)
+    f = point_source((nx, ny, nz), (8, 7, 6), H)
+    s = np.zeros_like(f)
+    g, its, rels, rc = p.g.grad(p.dev(f), p.dev(s), 1e-6)
+    assert rc == 0 and int(its[0, 1]) == 0 and float(torch.abs(g).max()) == 0.0, (its, rels)
+    nb = ctypes.c_size_t(0)
+    assert helm.lib().helm_grad_workspace_size(p.g._h, ctypes.byref(nb)) == 0 and nb.value > 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    gm = torch.empty(tuple(v + 1 for v in p.g.phys[::-1]), dtype=torch.float32, device="cuda")
+    fi = p.dev(f)
+    its2 = np.zeros(2, np.int32)
+    rel2 = np.zeros(2)
+    rc = helm.lib().helm_grad(p.g._h, ctypes.c_void_p(fi.data_ptr()), ctypes.c_void_p(fi.data_ptr()), 1, 1e-6,
+                              ctypes.c_void_p(gm.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb.value - 256,
+                              its2.ctypes.data, rel2.ctypes.data)
+    assert rc == -2
