@@ -314,6 +314,18 @@ __device__ void norm_epilogue(const RedBuf &rb, int nblocks, KState *st) {
     }
 }
 
+// Stencil outputs are stored with the non-temporal hint: the fine-level apply at 352^3 ran
+// 3% faster (0.279 -> 0.271 ms) with the solve unchanged.  Choosing the hint per level at
+// run time made every stencil slower (code generation of the march), so it is unconditional.
+__device__ __forceinline__ void st_nt(c32 *p, c32 v) {
+    const long long b = ((long long)__float_as_int(v.im) << 32) | (unsigned)__float_as_int(v.re);
+    __builtin_nontemporal_store(b, reinterpret_cast<long long *>(p));
+}
+__device__ __forceinline__ void st_nt(c64 *p, c64 v) {
+    __builtin_nontemporal_store(v.re, &p->re);
+    __builtin_nontemporal_store(v.im, &p->im);
+}
+
 template <typename T>
 __device__ __forceinline__ const T *plane_ptr(const T *base, long long plane_stride, int z) {
     return base + (long long)z * plane_stride;
@@ -481,7 +493,7 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
             TY ov;
             ov.re = res.r;
             ov.im = res.i;
-            *reinterpret_cast<TY *>(reinterpret_cast<char *>(yp_) + e0 * (unsigned)sizeof(TY)) = ov;
+            st_nt(reinterpret_cast<TY *>(reinterpret_cast<char *>(yp_) + e0 * (unsigned)sizeof(TY)), ov);
             if (NORM) nrm += (double)res.r * (double)res.r + (double)res.i * (double)res.i;
         }
     };
