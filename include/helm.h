@@ -152,6 +152,11 @@ helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, v
  * Returns HELM_NOT_CONVERGED (gradient still written) if a solve spent
  * max_outer preconditioner calls. */
 helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes);
+
+/* grad_c = grad_m * dm/dc = grad_m * (-2 / c^3): a gradient with respect to the squared
+ * slowness (as helm_grad returns it) turned into one with respect to the velocity c the
+ * hierarchy was built from.  Both DEVICE float[(nz+1)(ny+1)(nx+1)], physical nodes; may alias. */
+helm_status helm_grad_to_velocity(helm_hierarchy *H, const float *grad_m, float *grad_c);
 helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int nrhs, double tol, float *grad_m,
                       void *workspace, size_t ws_bytes, int *iters, double *relres);
 

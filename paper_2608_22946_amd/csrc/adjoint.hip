@@ -476,6 +476,25 @@ hipError_t launch_grad_node(const LevelArgs<double> &L, const c64 *v, const c64 
     return hipGetLastError();
 }
 
+// grad_c = grad_m * dm/dc = grad_m * (-2 / c^3) at the physical nodes; c from the fine-level velocity,
+// whose node p + n_pml (per axis) is physical node p
+__global__ void __launch_bounds__(256) k_grad_to_velocity(const float *grad_m, const float *__restrict__ vel, Geom F,
+                                                         int n_pml, int nxp, int nyp, int nzp, float *grad_c) {
+    const int px = blockIdx.x * kTX + threadIdx.x, py = blockIdx.y * kTY + threadIdx.y, pz = blockIdx.z;
+    if (px > nxp || py > nyp || pz > nzp) return;
+    const double c = vel[(long long)(pz + n_pml) * F.sy + (long long)(py + n_pml) * F.sx + px + n_pml];
+    const long long p = ((long long)pz * (nyp + 1) + py) * (nxp + 1) + px;
+    grad_c[p] = (float)((double)grad_m[p] * (-2.0 / (c * c * c)));
+}
+
+hipError_t launch_grad_to_velocity(const float *grad_m, const float *vel, const Geom &fine, int n_pml,
+                                   const int nphys[3], float *grad_c, hipStream_t s) {
+    const dim3 grid((unsigned)((nphys[0] + kTX) / kTX), (unsigned)((nphys[1] + kTY) / kTY), (unsigned)(nphys[2] + 1));
+    hipLaunchKernelGGL(k_grad_to_velocity, grid, dim3(kTX, kTY), 0, s, grad_m, vel, fine, n_pml, nphys[0], nphys[1],
+                       nphys[2], grad_c);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_xi_scale(const Geom &F, const c64 *fac, const T *in, T *out, bool inverse, hipStream_t s) {
     using R = real_of<T>;

@@ -1018,6 +1018,13 @@ helm_status helm_dims(const helm_hierarchy *H, int level, int dims[3]) {
     return HELM_OK;
 }
 
+helm_status helm_grad_to_velocity(helm_hierarchy *H, const float *grad_m, float *grad_c) {
+    if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
+    if (!grad_m || !grad_c) return fail(H, HELM_EINVAL, "invalid gradient-conversion arguments");
+    HIP_TRY(launch_grad_to_velocity(grad_m, H->vel[0], H->geom[0], H->n_pml, H->nphys, grad_c, H->s));
+    return HELM_OK;
+}
+
 helm_status helm_apply(helm_hierarchy *H, int level, int op, const void *x, void *y) {
     if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
     const bool fine_only = op == HELM_OP_Q || op == HELM_OP_QT || op == HELM_OP_DA || op == HELM_OP_DQ;

@@ -194,6 +194,8 @@ hipError_t launch_grad_node(const LevelArgs<double> &L, const c64 *v, const c64 
 // in may equal out (then nodes off the PML are not touched)
 template <typename T>
 hipError_t launch_xi_scale(const Geom &F, const c64 *fac, const T *in, T *out, bool inverse, hipStream_t s);
+hipError_t launch_grad_to_velocity(const float *grad_m, const float *vel, const Geom &fine, int n_pml,
+                                   const int nphys[3], float *grad_c, hipStream_t s);
 hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, const int nphys[3], float *out,
                             hipStream_t s);
 

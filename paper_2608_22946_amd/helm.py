@@ -36,7 +36,7 @@ class HelmOptions(ctypes.Structure):
 
 
 EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_grad",
-            "helm_grad_workspace_size", "helm_destroy",
+            "helm_grad_workspace_size", "helm_grad_to_velocity", "helm_destroy",
             "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_residual_restrict", "helm_jacobi",
             "helm_restrict",
             "helm_prolong_add", "helm_bottom", "helm_vcycle", "helm_coarse_solve", "helm_smooth", "helm_precond",
@@ -59,6 +59,7 @@ def lib():
         L.helm_solve.argtypes = [P, P, I, D, P, P, P]
         L.helm_grad.argtypes = [P, P, P, I, D, P, P, _c_size_t, P, P]
         L.helm_grad_workspace_size.argtypes = [P, ctypes.POINTER(_c_size_t)]
+        L.helm_grad_to_velocity.argtypes = [P, P, P]
         L.helm_destroy.argtypes = [P]
         L.helm_destroy.restype = None
         L.helm_last_error.argtypes = [P]
@@ -290,6 +291,12 @@ class Hierarchy:
         _check(rc, self._h, allow_not_converged=True)
         return g, its, rel, rc
 
+    def grad_to_velocity(self, grad_m, out=None):
+        """dJ/dc from dJ/dm (m = 1/c^2) on the physical nodes, with the hierarchy's velocity."""
+        g = torch.empty_like(grad_m) if out is None else out
+        _check(lib().helm_grad_to_velocity(self._h, _ptr(grad_m), _ptr(g)), self._h)
+        return g
+
     def solve(self, f, tol, out=None):
         """u = Q v with A v = Q f; f of shape (nrhs, ...) or a single grid function."""
         single = f.dim() == 3
@@ -305,3 +312,31 @@ class Hierarchy:
         if single:
             return u[0], int(its[0]), float(rel[0]), rc
         return u, its, rel, rc
+
+
+class _Solve(torch.autograd.Function):
+    """u = Q_h v, A_h(c) v = Q_h f, differentiable in the physical velocity c through helm_grad
+    (the incoming gradient g of a real loss L is the adjoint source: dL = Re sum conj(g) du).
+    No gradient flows to f."""
+
+    @staticmethod
+    def forward(ctx, vel, f, h, omega, n_pml, tol, kwargs):
+        hier = Hierarchy(vel.detach(), h, omega, n_pml, device=f.device, **kwargs)
+        u, its, rel, rc = hier.solve(f, tol)
+        ctx.hier, ctx.tol = hier, tol
+        ctx.save_for_backward(f)
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        (f,) = ctx.saved_tensors
+        gm, its, rel, rc = ctx.hier.grad(f, gu.to(f.dtype).contiguous(), ctx.tol)
+        gc = ctx.hier.grad_to_velocity(gm)
+        return gc, None, None, None, None, None, None
+
+
+def solve(vel, f, h, omega, n_pml, tol, **kwargs):
+    """Differentiable solve: u (same shape as f) for the physical velocity vel (torch float32 tensor
+    of shape (nz+1, ny+1, nx+1); gradients flow to it) and the source f on the total grid.  kwargs go
+    to Hierarchy (precision, table, lanes, ...)."""
+    return _Solve.apply(vel, f, float(h), float(omega), int(n_pml), float(tol), kwargs)

@@ -528,3 +528,33 @@ def test_grad_edge_cases():
                               ctypes.c_void_p(gm.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb.value - 256,
                               its2.ctypes.data, rel2.ctypes.data)
     assert rc == -2
+
+
+def test_autograd_velocity_gradient():
+    """helm.solve is differentiable in the physical velocity: for L = sum |w u|^2 the
+    autograd gradient (helm_grad, then dm/dc = -2/c^3) matches central differences of L
+    along a random float32-representable direction (FP64 solves to 1e-11)."""
+    from paper_2608_22946_amd import helm
+    vel = grf_velocity(16, 12, 12, seed=44, corr_len=4.0).astype(np.float32)
+    table = load_iofd_table()
+    omega = omega_for_ppw(float(vel.min()), H)
+    N = (20, 16, 16)
+    f = torch.from_numpy(point_source(N, (9, 8, 7), H)).cuda()
+    w = torch.from_numpy(random_complex(N, 45)).cuda()
+
+    def loss(v, grad):
+        vt = torch.from_numpy(v).cuda().requires_grad_(grad)
+        u = helm.solve(vt, f, H, omega, 2, 1e-11, precision="fp64", table=table)
+        L = torch.sum(torch.abs(w * u) ** 2)
+        if grad:
+            L.backward()
+            return float(L.detach()), vt.grad.detach().cpu().numpy().astype(np.float64)
+        return float(L), None
+
+    L0, g = loss(vel, True)
+    r = np.random.default_rng(46).uniform(-1.0, 1.0, vel.shape)
+    vp = (vel * (1 + 1e-5 * r)).astype(np.float32)
+    vm = (vel * (1 - 1e-5 * r)).astype(np.float32)
+    fd = loss(vp, False)[0] - loss(vm, False)[0]
+    an = float(np.sum(g * (vp.astype(np.float64) - vm.astype(np.float64))))
+    assert np.isfinite(L0) and abs(fd - an) <= 1e-4 * abs(fd), (fd, an)
