@@ -195,6 +195,19 @@ def test_smooth_cycle_lengths(m_h, x0):
     assert err <= 1e-10, err
 
 
+@pytest.mark.parametrize("nJ", [1, 2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bottom_jacobi_counts(nJ, precision):
+    """C_4h with one, two (the fused two-sweep stencil) and three Jacobi sweeps per
+    basis step against the checker, on a 4h level of 33 x 11 x 13 cells."""
+    vel = grf_velocity(124, 36, 44, seed=16, corr_len=6.0)
+    p = Pair(vel, 4, precision, nJ_4h=nJ)
+    q = p.rand(2, 216)
+    e = to_np(p.g.bottom(p.dev(q)))
+    err = rel(e, p.o.bottom(q.astype(complex)))
+    assert err <= p.tol(1e-9, 2e-3), err
+
+
 def test_precond(pair):
     r = pair.rand(0, 206)
     z = to_np(pair.g.precond(pair.dev(r)))
@@ -230,6 +243,8 @@ def test_extreme_aspect_grids(phys, npml):
         g, x = p.rand(level, 520 + level), p.rand(level, 530 + level)
         c = to_np(p.g.residual_restrict(level, 1, p.dev(g), p.dev(x)))
         assert rel(c, p.o.restrict(level, p.o.residual(level, 1, g, x))) <= 1e-12
+    q = p.rand(2, 540)
+    assert rel(to_np(p.g.bottom(p.dev(q))), p.o.bottom(q)) <= 1e-9
 
 
 def test_no_pml_box():
