@@ -291,7 +291,7 @@ def main():
                     help="time the adjoint misfit gradient on the benchmark workload instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see the sharding design).",
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (sharding is a design only).",
               file=sys.stderr)
         sys.exit(2)
     if args.paper_table:
