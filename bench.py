@@ -67,7 +67,7 @@ def recorded_traffic(nodes):
 
 
 def cpu_baseline(vel, omega, table, gpu_pc_calls):
-    """The FP64 reference checker on the host cores: one preconditioner
+    """The FP64 oracle on the host cores: one preconditioner
     application (Algorithm 1) on the full workload, scaled to seconds per
     right-hand side by the GPU run's preconditioner-call count."""
     from oracle.oracle import Hierarchy as OracleHierarchy

@@ -1,4 +1,4 @@
-"""ctypes front end of the FP64 reference checker (helm_oracle.c).
+"""ctypes front end of the FP64 oracle (helm_oracle.c).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the library or its binding.
@@ -74,7 +74,7 @@ def _c(a, dtype=np.complex128):
 
 
 class Hierarchy:
-    """The three grid levels (h, 2h, 4h) of one problem, held by the checker."""
+    """The three grid levels (h, 2h, 4h) of one problem, held by the oracle."""
 
     def __init__(self, vel_phys, h, omega, n_pml, table, params=None):
         from workloads.table import table_flat

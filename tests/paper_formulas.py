@@ -1,7 +1,7 @@
 """Closed forms printed in the paper, written out in numpy for the CPU pins.
 
 Each function states the passage it transcribes.  These are used to check the
-reference checker (and through it the GPU library) against the paper:
+oracle (and through it the GPU library) against the paper:
 plane-wave symbols, the Dirichlet sine-basis diagonalisation, grid-transfer
 symbols and the Jacobi polynomial.  Hermite evaluation here goes through
 scipy's CubicHermiteSpline, a library routine independent of both

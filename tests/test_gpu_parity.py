@@ -1,5 +1,5 @@
 """GPU parity: every step of the hot path through the C ABI against the FP64
-reference checker on the same seeded inputs.
+oracle on the same seeded inputs.
 
 Bars: FP64 stencil-type kernels <= 1e-12 relative L2, FP32 <= 1e-6; nested
 Krylov maps in FP64 within the rounding amplification of their small dense
@@ -28,7 +28,7 @@ def to_np(t):
 
 
 class Pair:
-    """GPU hierarchy and reference checker built from identical inputs."""
+    """GPU hierarchy and oracle built from identical inputs."""
 
     def __init__(self, vel, n_pml, precision, table=None, tiling=None, **params):
         from oracle.oracle import Hierarchy as OH
@@ -86,7 +86,7 @@ def test_residual(pair, level, op):
 
 @pytest.mark.parametrize("level,op", [(0, 0), (0, 1), (1, 1), (1, 0)])
 def test_residual_restrict(pair, level, op):
-    """Fused R (g - op x) against the checker's residual followed by its restriction."""
+    """Fused R (g - op x) against the oracle's residual followed by its restriction."""
     g, x = pair.rand(level, 31 + level), pair.rand(level, 41 + op)
     c = to_np(pair.g.residual_restrict(level, op, pair.dev(g), pair.dev(x)))
     ref = pair.o.restrict(level, pair.o.residual(level, op, g.astype(complex), x.astype(complex)))
@@ -147,7 +147,7 @@ def test_vec_orthonormalize(pair, level, k):
     assert rel(to_np(wt).ravel(), r / np.linalg.norm(r)) <= pair.tol(1e-12, 1e-5)
 
 
-# ---- nested maps (FP64 bars below; FP32 reports the gap to the FP64 checker) ----
+# ---- nested maps (FP64 bars below; FP32 reports the gap to the FP64 oracle) ----
 
 def test_bottom(pair):
     q = pair.rand(2, 201)
@@ -184,7 +184,7 @@ def test_smooth(pair, x0):
 @pytest.mark.parametrize("x0", [False, True])
 def test_smooth_cycle_lengths(m_h, x0):
     """S_h with m_h = 1 takes the s-step (Gram) path, m_h = 3 the Arnoldi path; both
-    must give the checker's GMRES(m_h) iterate (FP64)."""
+    must give the oracle's GMRES(m_h) iterate (FP64)."""
     vel = grf_velocity(60, 20, 28, seed=14, corr_len=5.0)
     p = Pair(vel, 4, "fp64", m_h=m_h)
     g = p.rand(0, 214)
@@ -199,7 +199,7 @@ def test_smooth_cycle_lengths(m_h, x0):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_bottom_jacobi_counts(nJ, precision):
     """C_4h with one, two (the fused two-sweep stencil) and three Jacobi sweeps per
-    basis step against the checker, on a 4h level of 33 x 11 x 13 cells."""
+    basis step against the oracle, on a 4h level of 33 x 11 x 13 cells."""
     vel = grf_velocity(124, 36, 44, seed=16, corr_len=6.0)
     p = Pair(vel, 4, precision, nJ_4h=nJ)
     q = p.rand(2, 216)
@@ -323,7 +323,7 @@ def test_solve_small_config_fp64():
                          ids=["tz4-split", "tz32-one"])
 def test_solve_fixed_tiling_fp32(tiling):
     """FP32 solve with the tiling fixed: the outer restart residual norm runs
-    through the split launches; the answer matches the FP64 checker's within
+    through the split launches; the answer matches the FP64 oracle's within
     the spread of two solves stopped at relative residual 1e-6."""
     n, npml = 44, 10
     vel = grf_velocity(n, n, n, seed=21, corr_len=8.0)
@@ -423,7 +423,7 @@ def test_c2_sampled_apply(c2):
 
 def test_c2_residual_restrict(c2):
     """Fused R (g - A x) fine -> 2h and R (g - B x) 2h -> 4h at the full size, every coarse node against the
-    checker's residual and restriction."""
+    oracle's residual and restriction."""
     p, _ = c2
     rng = np.random.default_rng(6)
     for level, op in [(0, 0), (1, 1)]:
@@ -437,7 +437,7 @@ def test_c2_residual_restrict(c2):
 
 def test_c2_jacobi(c2):
     """Fused two-sweep Jacobi at the full size on every level (A_h with omega_h; B_2h, B_4h as in the
-    V-cycle and the bottom solver), every node against the checker."""
+    V-cycle and the bottom solver), every node against the oracle."""
     p, _ = c2
     rng = np.random.default_rng(7)
     for level, op, w in [(0, 0, 0.8), (1, 1, 0.8), (2, 1, 0.2)]:
@@ -448,7 +448,7 @@ def test_c2_jacobi(c2):
 
 
 def test_c2_solve_residual(c2):
-    """FP32 solve to 1e-6 on the full workload; the FP64 checker recomputes
+    """FP32 solve to 1e-6 on the full workload; the FP64 oracle recomputes
     ||Q f - A u|| / ||Q f|| (Q = I table so that u is the iterate)."""
     p, vel = c2
     N = 352
@@ -468,7 +468,7 @@ def test_c2_solve_residual(c2):
 
 @pytest.mark.parametrize("level,op", [(0, 5), (0, 6), (0, 7), (1, 5), (1, 6), (2, 6)])
 def test_apply_transposed(pair, level, op):
-    """A^T, B^T (any level) and Q_h^T against the checker's transposes (scatter of rows)."""
+    """A^T, B^T (any level) and Q_h^T against the oracle's transposes (scatter of rows)."""
     x = pair.rand(level, 301 + level)
     y = to_np(pair.g.apply(level, op, pair.dev(x)))
     ref = pair.o.apply_t(level, op - 5, x.astype(complex))
@@ -478,7 +478,7 @@ def test_apply_transposed(pair, level, op):
 
 @pytest.mark.parametrize("op", [8, 9])
 def test_apply_row_derivative(pair, op):
-    """y_i = (d_i A_h x)_i and (d_i Q_h x)_i, m = 1/c^2, against the checker."""
+    """y_i = (d_i A_h x)_i and (d_i Q_h x)_i, m = 1/c^2, against the oracle."""
     x = pair.rand(0, 311)
     y = to_np(pair.g.apply(0, op, pair.dev(x)))
     ref = pair.o.apply_dm(0 if op == 8 else 2, x.astype(complex))
@@ -487,9 +487,9 @@ def test_apply_row_derivative(pair, op):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_grad_matches_checker(precision):
+def test_grad_matches_oracle(precision):
     """dJ/dm at the physical nodes (forward + adjoint solve, row-local assembly, PML
-    nodes summed onto their nearest physical node) against the checker's gradient,
+    nodes summed onto their nearest physical node) against the oracle's gradient,
     whose own central-difference pin is a CPU test; two right-hand sides summed."""
     vel = grf_velocity(24, 20, 16, seed=41, corr_len=5.0)
     p = Pair(vel, 4, precision)

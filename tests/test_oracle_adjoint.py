@@ -1,4 +1,4 @@
-"""Pins of the checker's adjoint pieces: the transposed operators against the
+"""Pins of the oracle's adjoint pieces: the transposed operators against the
 transposed dense matrices of the (separately pinned) forward operators, the
 row derivatives in m = 1/c^2 against central differences of the forward
 operators, and the whole gradient against central differences of a misfit
@@ -48,7 +48,7 @@ def _extend(Hh, phys):
 
 
 def _perturbed(oracle_lib, table, vel, eps, seed):
-    """Velocities c0 (1 +- eps r) rounded to float32 (the checker's input type) and
+    """Velocities c0 (1 +- eps r) rounded to float32 (the oracle's input type) and
     the exact squared-slowness difference m+ - m- they represent.  The coefficient
     tables are cubic Hermite interpolants, only C^1 at their knots, so the step is
     kept small (1e-5) to leave few nodes whose difference straddles a knot."""

@@ -1,4 +1,4 @@
-"""Pins of the reference checker's level operators (A, B, Q, diagonal) against
+"""Pins of the oracle's level operators (A, B, Q, diagonal) against
 closed forms of the paper: plane-wave symbols, sine-basis diagonalisation of
 the Dirichlet box, the separable (Kronecker) special case with PML, the
 7-point textbook reduction, shell/tensor agreement and cube symmetry."""

@@ -1,4 +1,4 @@
-"""Pins of the checker's Krylov maps, shifted V-cycle, Algorithm 1 and outer
+"""Pins of the oracle's Krylov maps, shifted V-cycle, Algorithm 1 and outer
 solve: minimal-residual property against dense least squares, the two-grid
 error operator of eq. lfa-shifted-vcycle / eq. lfa-shifted-inverse in the
 Dirichlet sine basis, a dense direct solve, and the outgoing Green function."""

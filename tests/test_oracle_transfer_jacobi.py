@@ -1,4 +1,4 @@
-"""Pins of the checker's grid transfers and damped Jacobi map:
+"""Pins of the oracle's grid transfers and damped Jacobi map:
 R = 2^-3 P^* (Sec. 3.1), trilinear reproduction, the transfer symbol of
 eq. lfa-transfer-symbol, and the Jacobi polynomial of eq. lfa-bottom-inverse
 in the Dirichlet sine basis."""

@@ -2,7 +2,7 @@
 
 Nothing in this package performs any step of the method: it only produces
 velocity models, point sources, random test vectors and the coefficient table
-file. Both the GPU library and the reference checker consume these inputs.
+file. Both the GPU library and the oracle consume these inputs.
 
 Array conventions
 -----------------

@@ -39,7 +39,7 @@ the reconstructed field, not the solver.
 
 This script is not imported by any runtime code; its output,
 iofd_table.json, is an input of the method (like the velocity model) that
-the solver library and the reference checker both receive.
+the solver library and the oracle both receive.
 
 Run:  python workloads/derive_iofd_table.py   (writes workloads/iofd_table.json)
 """
