@@ -218,14 +218,17 @@ helm_status helm_precond(helm_hierarchy *H, const void *r, void *z);
 
 /* Krylov vector kernel: out[j] = sum_i conj(V_j[i]) w[i] for j < k, and
  * out[k] = ||w||^2 (imaginary part 0), accumulated in FP64.
- *   V   HOST array of k DEVICE pointers (level vectors), 0 <= k <= 16
- *   out HOST double[2*(k+1)] (complex pairs) */
+ *   V   HOST array of k DEVICE pointers (level vectors), 0 <= k <= 12
+ *   out HOST double[2*(k+1)] (complex pairs)
+ * Returns HELM_EINVAL for k outside 0..12. */
 helm_status helm_vec_dots(helm_hierarchy *H, int level, int k, const void *const *V, const void *w, double *out);
 
 /* One Arnoldi orthogonalisation step (classical Gram-Schmidt, two passes):
  * w <- (w - V h) / ||w - V h||, with h = V^* w accumulated over both passes.
- *   V   HOST array of k DEVICE pointers (orthonormal level vectors), 1 <= k <= 16
- *   out HOST double[2*(k+1)]: h_0..h_{k-1} then ||w - V h|| */
+ *   V   HOST array of k DEVICE pointers (orthonormal level vectors), 1 <= k <= 12
+ *   out HOST double[2*(k+1)]: h_0..h_{k-1} then ||w - V h||
+ * Returns HELM_EINVAL for k outside 1..12.  If w lies in the span of V (w - V h
+ * vanishes exactly), w is set to zero. */
 helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const void *const *V, void *w,
                                     double *out);
 

@@ -582,7 +582,9 @@ typedef void (*or_linop)(const or_hier *H, void *ctx, const cplx *in, cplx *out)
 
 /* x <- result of `cycles` restarted cycles of length m for op x = g started at
  * x (x holds x0 on entry), right preconditioned by prec (stored Z vectors).
- * A cycle ends early on a happy breakdown h_{k+1,k} <= 1e-14 beta.  Returns
+ * A cycle ends early on a happy breakdown: the new direction w = op(prec(v_k))
+ * lies in the Krylov space, h_{k+1,k} = ||w - V h|| <= 1e-14 ||w|| (a
+ * scale-free test: the iterate scales with g).  Returns
  * the number of Arnoldi steps done. */
 static int fgmres(const or_hier *H, size_t n, or_linop op, void *opctx, or_linop prec, void *pctx,
                   const cplx *g, cplx *x, int m, int cycles, int x0_is_zero)
@@ -614,6 +616,7 @@ static int fgmres(const or_hier *H, size_t n, or_linop op, void *opctx, or_linop
         for (int k = 0; k < m; ++k) {
             prec(H, pctx, V[k], Z[k]);
             op(H, opctx, Z[k], w);
+            double wn = vnorm(n, w);
             for (int j = 0; j <= k; ++j) {
                 cplx hjk = vdot(n, V[j], w);
                 Hm[j * m + k] = hjk;
@@ -647,7 +650,7 @@ static int fgmres(const or_hier *H, size_t n, or_linop op, void *opctx, or_linop
             gv[k] = cs[k] * gv[k];
             kk = k + 1;
             ++steps;
-            if (hk1 <= 1e-14 * beta) break;
+            if (hk1 <= 1e-14 * wn) break;
             vcopy(n, w, V[k + 1]);
             vscale(n, 1.0 / hk1, V[k + 1]);
         }
@@ -1056,6 +1059,7 @@ static int outer_fgmres(const or_hier *H, int transposed, const cplx *b, cplx *v
                 precond(H, V[k], Z[k]);
                 ++its;
                 outer_apply(H, transposed, Z[k], w);
+                double wn = vnorm(n, w);
                 for (int j = 0; j <= k; ++j) {
                     cplx hjk = vdot(n, V[j], w);
                     Hm[j * m + k] = hjk;
@@ -1086,7 +1090,7 @@ static int outer_fgmres(const or_hier *H, int transposed, const cplx *b, cplx *v
                 gv[k + 1] = -conj(sn[k]) * gv[k];
                 gv[k] = cs[k] * gv[k];
                 kk = k + 1;
-                if (cabs(gv[k + 1]) / bn <= tol || hk1 <= 1e-14 * beta) break;
+                if (cabs(gv[k + 1]) / bn <= tol || hk1 <= 1e-14 * wn) break;
                 if (max_outer > 0 && its >= max_outer) break;
                 vcopy(n, w, V[k + 1]);
                 vscale(n, 1.0 / hk1, V[k + 1]);

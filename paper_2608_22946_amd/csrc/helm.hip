@@ -70,6 +70,13 @@ struct helm_hierarchy {
     std::string err;
 };
 
+namespace helm {
+helm_status thread_error(helm_status st, const char *msg) {
+    g_thread_error = msg;
+    return st;
+}
+}  // namespace helm
+
 namespace {
 
 std::mutex g_err_mutex;   // lanes of one helm_solve may report errors concurrently

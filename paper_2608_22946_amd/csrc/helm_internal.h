@@ -20,7 +20,14 @@ constexpr int kTileX = 62;      // output nodes per wavefront along x (64 lanes,
 constexpr int kWavesY = 4;      // wavefronts (rows y) per workgroup
 constexpr int kRedBlocks = 1024;
 constexpr int kRedStride = kMMax + 2;   // partial-sum slots per block (dots + norm)
-constexpr double kBreakdown = 1e-14;    // happy-breakdown threshold h_{k+1,k} <= 1e-14 beta
+constexpr int kRedMaxBlocks = 256;      // most blocks of a vector reduction (red_blocks)
+// complex partial-sum slots per reduction block: the larger of the s-step Gram
+// matrix's (kM4Max + 1)(kM4Max + 2)/2 entries and the dots' kRedStride
+constexpr int kRedSlots = (kM4Max + 1) * (kM4Max + 2) / 2 > kRedStride ? (kM4Max + 1) * (kM4Max + 2) / 2 : kRedStride;
+// Happy breakdown: the newest direction w = op(prec(v_k)) lies in the Krylov space,
+// h_{k+1,k} = ||w - V h|| <= kBreakdown ||w|| (scale-free: a scaled right-hand side
+// gives the scaled iterate)
+constexpr double kBreakdown = 1e-14;
 // Selective reorthogonalisation: the second classical Gram-Schmidt pass runs only
 // when the first left less than this fraction of ||w||^2, i.e. ||w - V h|| <
 // ||w|| / 32.  One pass then keeps the new vector orthogonal to about 32 units
@@ -82,6 +89,7 @@ struct KState {
     double scale;                    // multiplier that normalises the newest basis vector
     double vs0;                      // the first basis vector is kept unnormalised: V_0 = vs0 * (stored vector)
     double hk1;                      // last subdiagonal entry
+    double wn;                       // ||w|| of the newest column before orthogonalisation
     int kk;                          // Arnoldi columns in the current cycle
     int breakdown;
     int nonfinite;
@@ -211,6 +219,9 @@ hipError_t launch_extend_velocity(const float *phys, const int nphys[3], int n_p
 hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, double *out, hipStream_t s);
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// record the message helm_last_error(NULL) returns on this thread; returns st
+helm_status thread_error(helm_status st, const char *msg);
 
 // Cross-block completion ticket without device-wide cache maintenance.
 // Partial results are written with agent-scope atomic stores (write-through

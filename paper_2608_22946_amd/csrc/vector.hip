@@ -12,8 +12,7 @@
 
 namespace helm {
 
-constexpr int kGramMax = (kM4Max + 1) * (kM4Max + 2) / 2;   // 45
-constexpr int kSlots = kGramMax > kRedStride ? kGramMax : kRedStride;
+constexpr int kSlots = kRedSlots;
 
 namespace {
 
@@ -175,8 +174,9 @@ __device__ void givens_column(KState *st, int k, double (*cr)[2], double hk1) {
     st->g[k][1] = c * gi;
     st->kk = k + 1;
     st->hk1 = hk1;
-    // column 0 was built from the unnormalised first vector (scaled by 1/vs0)
-    const bool ok = (k == 0 ? hk1 * st->vs0 : hk1) > kBreakdown * st->beta;
+    // h_{k+1,k} and ||w|| carry the same scale (also in column 0, built from the
+    // unnormalised first vector), so the test is scale-free
+    const bool ok = hk1 > kBreakdown * st->wn;
     st->scale = ok ? 1.0 / hk1 : 0.0;
     if (!ok) st->breakdown = 1;
     if (!(hk1 == hk1) || !(st->g[k + 1][0] == st->g[k + 1][0])) st->nonfinite = 1;
@@ -220,6 +220,7 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
                 st->h1[j][1] = tot[j].i;
             }
             st->reorth = 1;
+            st->wn = 0.0;   // no norm in this pass: only an exactly vanishing w - V h counts as breakdown
         } else if (EPI == EPI_ARNOLDI_SEL && NV > 0) {
             // selective second pass: if the first projection keeps at least
             // kReorthEta of ||w||^2, w - V h1 is orthogonal to a few units of
@@ -233,6 +234,7 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
                 c2 += tot[j].r * tot[j].r + tot[j].i * tot[j].i;
             }
             const double w2 = tot[NS - 1].r, r2 = w2 - c2;
+            st->wn = sqrt(w2);
             if (r2 >= kReorthEta * w2) {
                 for (int j = 0; j < NV; ++j) {
                     st->h2[j][0] = tot[j].r;
@@ -590,7 +592,7 @@ __global__ void __launch_bounds__(256) k_velocity_check(const float *__restrict_
 int red_blocks(long long n) {
     long long b = (n + 4 * kRedThreads - 1) / (4 * kRedThreads);
     if (b < 1) b = 1;
-    if (b > 256) b = 256;
+    if (b > kRedMaxBlocks) b = kRedMaxBlocks;
     return (int)b;
 }
 
