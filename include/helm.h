@@ -232,6 +232,28 @@ helm_status helm_vec_dots(helm_hierarchy *H, int level, int k, const void *const
 helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const void *const *V, void *w,
                                     double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): helm_vec_dots on plain
+ * vectors, without a hierarchy, with the result left in device memory.  The
+ * reduction's per-block partial sums and its completion counter live in a
+ * library-owned static device array of at most 192 KiB per GPU, held from the
+ * first call on that GPU until the process ends; the call performs no hipMalloc,
+ * hipFree or other allocation and does not synchronise.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams or
+ * threads) race and give wrong sums.
+ *   precision HELM_FP32 (complex64 vectors) or HELM_FP64 (complex128 vectors)
+ *   n         entries per vector, 1 <= n <= 2^40
+ *   k         0 <= k <= 12
+ *   V         HOST array of k DEVICE pointers (n entries each)
+ *   w         DEVICE vector of n entries
+ *   out       DEVICE double[2*(k+1)]: conj(V_j) . w for j < k, then ||w||^2 (imaginary
+ *             part 0), accumulated in FP64 (the sums of helm_vec_dots for the same n)
+ *   stream    hipStream_t the work is enqueued on (NULL = default stream)
+ * Returns HELM_EINVAL (message in helm_last_error(NULL)) for a bad precision, n
+ * or k, or a NULL pointer, before any device work. */
+helm_status helm_vec_dots_static(int precision, long long n, int k, const void *const *V, const void *w,
+                                 double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

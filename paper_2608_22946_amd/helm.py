@@ -40,7 +40,7 @@ EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_s
             "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_residual_restrict", "helm_jacobi",
             "helm_restrict",
             "helm_prolong_add", "helm_bottom", "helm_vcycle", "helm_coarse_solve", "helm_smooth", "helm_precond",
-            "helm_vec_dots", "helm_vec_orthonormalize"]
+            "helm_vec_dots", "helm_vec_orthonormalize", "helm_vec_dots_static"]
 
 _lib = None
 
@@ -76,6 +76,7 @@ def lib():
         L.helm_smooth.argtypes = [P, P, P, P]
         L.helm_vec_dots.argtypes = [P, I, I, P, P, P]
         L.helm_vec_orthonormalize.argtypes = [P, I, I, P, P, P]
+        L.helm_vec_dots_static.argtypes = [I, ctypes.c_longlong, I, P, P, P, P]
         _lib = L
     return _lib
 
@@ -312,6 +313,27 @@ class Hierarchy:
         if single:
             return u[0], int(its[0]), float(rel[0]), rc
         return u, its, rel, rc
+
+
+def vec_dots_static(V, w, out=None):
+    """helm_vec_dots_static: (conj(V_j) . w, ||w||^2) in FP64 into a device float64 tensor of
+    2 (k + 1) entries (complex pairs), enqueued on torch's current stream, with no allocation
+    inside the library (its reduction scratch is a static device array)."""
+    k = len(V)
+    if w.dtype not in (torch.complex64, torch.complex128) or not w.is_contiguous() or w.device.type != "cuda":
+        raise ValueError("w must be a contiguous complex64 / complex128 CUDA tensor")
+    for v in V:
+        if v.dtype != w.dtype or v.numel() != w.numel() or not v.is_contiguous() or v.device != w.device:
+            raise ValueError("every V_j must match w in dtype, size and device")
+    if out is None:
+        out = torch.empty(2 * (k + 1), dtype=torch.float64, device=w.device)
+    elif out.dtype != torch.float64 or out.numel() < 2 * (k + 1) or not out.is_contiguous() or out.device != w.device:
+        raise ValueError("out must be a contiguous float64 tensor of at least 2 (k + 1) entries on w's device")
+    arr = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in V])
+    prec = FP64 if w.dtype == torch.complex128 else FP32
+    stream = torch.cuda.current_stream(w.device).cuda_stream
+    _check(lib().helm_vec_dots_static(prec, w.numel(), k, arr, _ptr(w), _ptr(out), ctypes.c_void_p(stream)))
+    return out
 
 
 class _Solve(torch.autograd.Function):

@@ -138,3 +138,13 @@ def test_calls_on_null_hierarchy(L):
     nb = ctypes.c_size_t(0)
     assert L.helm_grad_workspace_size(None, ctypes.byref(nb)) == -1
     L.helm_destroy(None)
+
+
+def test_static_dots_rejects_arguments_on_host(L):
+    """helm_vec_dots_static validates before touching the device (no GPU here)."""
+    w = ctypes.c_void_p(16)
+    assert L.helm_vec_dots_static(7, 10, 0, None, w, w, None) == -1           # precision
+    assert L.helm_vec_dots_static(helm.FP32, 0, 0, None, w, w, None) == -1    # n
+    assert L.helm_vec_dots_static(helm.FP32, 10, 13, None, w, w, None) == -1  # k > 12
+    assert L.helm_vec_dots_static(helm.FP32, 10, 2, None, w, w, None) == -1   # V missing
+    assert L.helm_vec_dots_static(helm.FP64, 10, 0, None, w, None, None) == -1  # out missing
