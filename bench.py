@@ -205,6 +205,118 @@ def multi_rhs(lane_counts=(1, 2, 4), seed=3):
         del Hh, u
 
 
+def c4_source(vel, npml, seed=4):
+    """Seeded source node (total-grid x, y, z) outside the inclusion (velocity below
+    3000 m/s) and at least 6 cells inside the physical box."""
+    rng = np.random.default_rng(seed)
+    n = vel.shape[0] - 1
+    while True:
+        p = rng.integers(6, n - 6, 3)
+        if vel[p[2], p[1], p[0]] < 3000.0:
+            return tuple(int(v) + npml for v in p)
+
+
+def c4_bench(precision, apply_reps, crop, crop_tol):
+    """Largest single-GPU workload: 768^3 + 16 PML cells (800^3 total, 5.1e8 nodes),
+    1500 m/s background with a seeded ellipsoidal 4500 m/s inclusion (semi-axes
+    150/120/90 cells) times (1 + 0.1 g), g a GRF of correlation length 20 cells, 6
+    points per wavelength at the minimum velocity, one seeded source outside the
+    inclusion, tol 1e-6.  One warm-up and one timed solve; the fine A_h apply timed
+    at this shape; then (crop > 0) the same physics on a crop^3 + 16 PML box around
+    the source, solved on the GPU to 1e-6 and by the FP64 oracle to crop_tol, compared
+    node by node.  One JSON line."""
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import ellipsoid_grf_velocity, load_iofd_table, point_source
+    from workloads.configs import omega_for_ppw
+
+    n, npml = 768, 16
+    N = n + 2 * npml
+    t0 = time.perf_counter()
+    vel = ellipsoid_grf_velocity(n, n, n, seed=4)
+    omega = omega_for_ppw(float(vel.min()), H)
+    src = c4_source(vel, npml)
+    t_gen = time.perf_counter() - t0
+    print(json.dumps({"c4": "inputs", "gen_s": round(t_gen, 1), "c_min": float(vel.min()),
+                      "c_max": float(vel.max()), "source": src}), flush=True)
+    table = load_iofd_table()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Hh = helm.Hierarchy(torch.from_numpy(vel), H, omega, npml, precision=precision, table=table, device=dev)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    nodes = int(np.prod(Hh.shape(0)))
+    cdt = Hh.cdtype
+    f = torch.zeros(Hh.shape(0), dtype=cdt, device=dev)
+    f[src[2], src[1], src[0]] = H ** -3
+    x = torch.randn(Hh.shape(0), dtype=cdt, device=dev)
+    y = torch.empty_like(x)
+    Hh.apply(0, helm.OP_A, x, out=y)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(apply_reps):
+        Hh.apply(0, helm.OP_A, x, out=y)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_apply = ev0.elapsed_time(ev1) / 1e3 / apply_reps
+    per_node = 36.0 if precision == "fp64" else 20.0
+    del x, y
+    print(json.dumps({"c4": "apply", "avg_launch_ms": round(t_apply * 1e3, 3),
+                      "GBs": round(per_node * nodes / t_apply / 1e9, 1)}), flush=True)
+    u = torch.empty_like(f)
+    _, its, rel, rc = Hh.solve(f, TOL, out=u.unsqueeze(0))     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, rel, rc = Hh.solve(f, TOL, out=u.unsqueeze(0))
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    out = {"metric": "time-to-rel.res 1e-6 per RHS + stencil-apply HBM GB/s vs peak", "value": round(t_solve, 3),
+           "unit": "s per RHS", "n_gpus": 1, "dtype": "f64" if precision == "fp64" else "f32",
+           "data": "synthetic", "precision": precision,
+           "config": {"workload": "ellipsoid-800: 768^3 + 16-cell PML, 1500 m/s with a seeded 4500 m/s ellipsoid "
+                                  "(150/120/90 cells) x (1 + 0.1 GRF), 6 ppw at c_min, 1 seeded source, tol 1e-6",
+                      "grid_total": N, "n_pml": npml, "nodes_fine": nodes, "source": list(src)},
+           "pc_calls": int(its), "relres": float(rel), "converged": rc == 0,
+           "solve_per_pc_ms": round(t_solve / max(int(its), 1) * 1e3, 2), "setup_s": round(t_setup, 3),
+           "roofline": {"bound": "hbm", "kernel": f"fine-level A_h apply (27-point IOFD, 800^3, {precision})",
+                        "achieved": round(per_node * nodes / t_apply / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(per_node * nodes / t_apply / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                        "alg_bytes_per_launch": per_node * nodes, "avg_launch_ms": round(t_apply * 1e3, 4)}}
+    print(json.dumps(out), flush=True)
+    Hh.close()
+    del Hh, f, u
+    torch.cuda.empty_cache()
+    if crop <= 0:
+        return
+    # ---- the same physics on a crop around the source: GPU (this precision) vs the FP64 oracle ----
+    from oracle.oracle import Hierarchy as OracleHierarchy
+    sp = np.array(src) - npml
+    lo = np.clip(sp - crop // 2, 0, n - crop)
+    vc = np.ascontiguousarray(vel[lo[2]:lo[2] + crop + 1, lo[1]:lo[1] + crop + 1, lo[0]:lo[0] + crop + 1])
+    del vel
+    Nc = crop + 2 * npml
+    s_loc = tuple(int(v) for v in sp - lo + npml)
+    fc = point_source((Nc, Nc, Nc), s_loc, H)
+    Hc = helm.Hierarchy(torch.from_numpy(vc), H, omega, npml, precision=precision, table=table, device=dev)
+    uc, its_c, rel_c, rc_c = Hc.solve(torch.from_numpy(fc.astype(np.complex128 if precision == "fp64"
+                                                                     else np.complex64)).to(dev), TOL)
+    ug = uc.cpu().numpy().astype(np.complex128)
+    Hc.close()
+    t0 = time.perf_counter()
+    O = OracleHierarchy(vc, H, omega, npml, table)
+    uo, its_o, rel_o, st_o = O.solve(fc, crop_tol)
+    t_or = time.perf_counter() - t0
+    O.close()
+    err = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+    print(json.dumps({"c4": "crop", "crop": f"{crop}^3 + {npml} PML around the source", "precision": precision,
+                      "gpu_pc_calls": int(its_c), "gpu_relres": float(rel_c), "oracle_pc_calls": its_o,
+                      "oracle_relres": rel_o, "oracle_s": round(t_or, 1),
+                      "rel_l2_error_vs_oracle": err}), flush=True)
+
+
 def grad_bench(steps, warmup, apply_reps, with_cpu):
     """Adjoint gradient on the benchmark workload: dJ/dm (m = 1/c^2) for the seeded point
     source and a synthetic adjoint source (seeded complex normal values at every physical
@@ -244,32 +356,54 @@ def grad_bench(steps, warmup, apply_reps, with_cpu):
     t_at = ev0.elapsed_time(ev1) / 1e3 / apply_reps
     del x, y
 
+    # forward solve keeping v (checkpoint), then the gradient from it: adjoint solve + assembly
     its = rel = g = None
+    v = torch.empty(f.shape, dtype=torch.complex128, device=dev)
+    u = torch.empty_like(f)
     for _ in range(warmup):
-        g, its, rel, rc = Hh.grad(f, s, TOL)
+        _, _, its_f, rel_f, rc_f = Hh.solve_checkpoint(f, TOL, out=u.unsqueeze(0), v_out=v.unsqueeze(0))
+        g, its, rel, rc = Hh.grad(f, s, TOL, v=v)
+    t_fwd = t_bwd = 0.0
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, its_f, rel_f, rc_f = Hh.solve_checkpoint(f, TOL, out=u.unsqueeze(0), v_out=v.unsqueeze(0))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g, its, rel, rc = Hh.grad(f, s, TOL, v=v)
+        torch.cuda.synchronize()
+        t_fwd += t1 - t0
+        t_bwd += time.perf_counter() - t1
+    t_fwd /= steps
+    t_bwd /= steps
+    # the same gradient with the forward solve inside helm_grad (no checkpoint), once
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        g, its, rel, rc = Hh.grad(f, s, TOL)
+    g2, its2, rel2, rc2 = Hh.grad(f, s, TOL)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    if rc != 0 or not rel.max() <= TOL or not bool(torch.isfinite(g).all()):
+    t_nockpt = time.perf_counter() - t0
+    gd = float(torch.linalg.vector_norm(g - g2) / torch.linalg.vector_norm(g2))
+    if rc != 0 or rc_f != 0 or not rel[0, 1] <= TOL or not rel_f <= TOL or not bool(torch.isfinite(g).all()):
         print(json.dumps({"error": "gradient solves did not reach the tolerance", "relres": rel.tolist()}))
         sys.exit(1)
     alg = 20.0 * nodes   # 8 B x + 4 B velocity read, 8 B y written per node
-    out = {"metric": "time per misfit gradient dJ/dm (forward + adjoint solve to 1e-6, assembly)",
-           "value": round(dt, 4), "unit": "s per gradient", "n_gpus": 1, "steps": steps, "warmup": warmup,
+    out = {"metric": "time per misfit gradient dJ/dm given the checkpointed forward field (adjoint solve to "
+                     "1e-6 + assembly)",
+           "value": round(t_bwd, 4), "unit": "s per gradient", "n_gpus": 1, "steps": steps, "warmup": warmup,
            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "grf-352-fp32 (as the main line) with a synthetic adjoint source on the "
                                   f"receiver plane z = {zr}", "source": list(src), "tol": TOL},
-           "pc_calls_forward": int(its[0, 0]), "pc_calls_adjoint": int(its[0, 1]),
-           "relres": [float(v) for v in rel[0]],
+           "forward_solve_s": round(t_fwd, 4), "forward_plus_gradient_s": round(t_fwd + t_bwd, 4),
+           "gradient_without_checkpoint_s": round(t_nockpt, 4),
+           "checkpoint_vs_resolve_rel_diff": gd,
+           "pc_calls_forward": int(its_f), "pc_calls_adjoint": int(its[0, 1]),
+           "relres": [float(rel_f), float(rel[0, 1])],
            "roofline": {"bound": "hbm", "kernel": "fine-level A_h^T apply (rows staged per plane in LDS, 352^3, fp32)",
                         "achieved": round(alg / t_at / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(alg / t_at / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
                         "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_at * 1e3, 4)}}
     if with_cpu:
-        out["cpu_baseline"] = cpu_baseline(vel, omega, table, int(its[0, 0]) + int(its[0, 1]))
+        out["cpu_baseline"] = cpu_baseline(vel, omega, table, int(its_f) + int(its[0, 1]))
         out["cpu_baseline"]["unit"] = "s per gradient (extrapolated)"
     print(json.dumps(out), flush=True)
 
@@ -291,6 +425,11 @@ def main():
                     help="run the 64-source 288^3 layered workload with 1, 2 and 4 concurrent lanes instead")
     ap.add_argument("--grad", action="store_true",
                     help="time the adjoint misfit gradient on the benchmark workload instead")
+    ap.add_argument("--c4", action="store_true",
+                    help="run the 800^3 ellipsoid workload (largest single-GPU case) instead")
+    ap.add_argument("--crop", type=int, default=128,
+                    help="with --c4: physical cells of the oracle-checked crop around the source (0: none)")
+    ap.add_argument("--crop-tol", type=float, default=1e-10, help="with --c4: the oracle's tolerance on the crop")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (sharding is a design only).",
@@ -304,6 +443,9 @@ def main():
         return
     if args.grad:
         grad_bench(args.steps, args.warmup, args.apply_reps, not args.no_cpu_baseline)
+        return
+    if args.c4:
+        c4_bench(args.precision, args.apply_reps, args.crop, args.crop_tol)
         return
 
     import torch
@@ -345,12 +487,21 @@ def main():
     alg_bytes = per_node * nodes[0]
     achieved = alg_bytes / t_apply / 1e9
     if args.profile_apply:
+        # the fused two-sweep Jacobi from zero on the fine level (A_h, omega_h 0.8), then a plain copy
+        # of known size for counter calibration
+        ev0.record(stream)
+        for _ in range(args.apply_reps):
+            Hh.jacobi(0, helm.OP_A, x, 2, 0.8, out=y)
+        ev1.record(stream)
+        ev1.synchronize()
+        t_jac = ev0.elapsed_time(ev1) / 1e3 / args.apply_reps
         z = torch.empty_like(x)
         for _ in range(args.apply_reps):
-            z.copy_(x)                                   # plain copy of known size, for counter calibration
+            z.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"apply_ms": t_apply * 1e3, "apply_GBs": achieved, "nodes": nodes[0],
-                          "copy_bytes_each_way": x.numel() * x.element_size(), "stencil_sha": stencil_hash()}))
+        print(json.dumps({"apply_ms": t_apply * 1e3, "apply_GBs": achieved, "jacobi2_ms": t_jac * 1e3,
+                          "nodes": nodes[0], "copy_bytes_each_way": x.numel() * x.element_size(),
+                          "stencil_sha": stencil_hash()}))
         return
     level_gbs = {}
     for lvl in (1, 2):

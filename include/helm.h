@@ -110,7 +110,9 @@ helm_status helm_workspace_size(int nx, int ny, int nz, int n_pml, const helm_op
 /* Build the operator hierarchy (Sec. 3.1): the velocity is extended into the
  * PML by its nearest physical value (Sec. 2.1) and sampled at the nodes of
  * each level; the per-axis PML factors (eq. pml-profile, half nodes averaged
- * before inversion) and the table are uploaded.
+ * before inversion) and the table are uploaded.  The stencil tilings not fixed
+ * by the options are timed on the first setup of a level shape and precision
+ * in the process (per device) and reused by later setups of that shape. 
  *   velocity  DEVICE float[(nz+1)(ny+1)(nx+1)], physical nodes, m/s, finite > 0
  *   h, omega  fine spacing (m) and angular frequency (rad/s), finite > 0
  *   workspace DEVICE, >= helm_workspace_size() bytes, 256-byte aligned, owned by
@@ -131,6 +133,13 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
 helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, int *iters,
                        double *relres);
 
+/* helm_solve that also keeps the forward solutions v (A_h v = Q_h f, u = Q_h v)
+ * in FP64 for a later helm_grad (checkpointed forward wavefields):
+ *   v  DEVICE complex128 [nrhs][total grid], written (must not alias f or u)
+ * Other arguments and returns as helm_solve. */
+helm_status helm_solve_checkpoint(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, void *v,
+                                  int *iters, double *relres);
+
 /* Gradient of a real misfit J(u) of the solutions u = Q_h v, A_h v = Q_h f
  * (eq. iofd-complete-system), with respect to the squared slowness m = 1/c^2
  * at the physical nodes, by the adjoint state.  Each row of A_h and Q_h takes
@@ -139,11 +148,15 @@ helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, v
  *   dJ/dm_i = Re[ conj(s_i) (d_i Q_h v)_i + mu_i ((d_i Q_h f)_i - (d_i A_h v)_i) ],
  * and a PML node, which takes the velocity of its nearest physical node
  * (Sec. 2.1), adds its term onto that node.  Per right-hand side: one forward
- * and one adjoint solve (outer FGMRES with A_h^T, the same preconditioner),
- * each to the true relative residual tol.
+ * solve (skipped when v_fwd is given) and one adjoint solve (outer FGMRES with
+ * A_h^T, the same preconditioner), each to the true relative residual tol.
  *   f, adj_src DEVICE [nrhs][total grid] precision vectors: sources, and the
  *              adjoint sources s defined by dJ = Re sum_i conj(s_i) du_i
  *              (for J = 1/2 ||u - d||^2: s = u - d)
+ *   v_fwd      DEVICE complex128 [nrhs][total grid]: the forward solutions as
+ *              helm_solve_checkpoint returns them for the same f, or NULL to
+ *              solve the forward problems here (then iters/relres report them;
+ *              with v_fwd their forward entries are 0)
  *   grad_m     DEVICE float[(nz+1)(ny+1)(nx+1)], physical nodes: dJ/dm summed
  *              over the right-hand sides (overwritten)
  *   workspace  DEVICE, >= helm_grad_workspace_size() bytes, 256-byte aligned
@@ -157,8 +170,8 @@ helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes);
  * slowness (as helm_grad returns it) turned into one with respect to the velocity c the
  * hierarchy was built from.  Both DEVICE float[(nz+1)(ny+1)(nx+1)], physical nodes; may alias. */
 helm_status helm_grad_to_velocity(helm_hierarchy *H, const float *grad_m, float *grad_c);
-helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int nrhs, double tol, float *grad_m,
-                      void *workspace, size_t ws_bytes, int *iters, double *relres);
+helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, const void *v_fwd, int nrhs, double tol,
+                      float *grad_m, void *workspace, size_t ws_bytes, int *iters, double *relres);
 
 void helm_destroy(helm_hierarchy *H);
 

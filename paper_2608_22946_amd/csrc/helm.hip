@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -60,10 +61,11 @@ struct helm_hierarchy {
     LevelArgs<double> Ld[3];
     // device buffers carved from the caller's workspace: shared, read-only during solves
     float *vel[3];
+    float *svel[3];      // FP32 mode: the scaled interpolation coordinate per node (LevelArgs::s)
     void *dinv[3][2];    // D^-1 of A_l and B_l per level, in the working precision
     float *wf[3][3];
     double *wd[3][3];
-    float *atab_f, *btab_f;
+    float *atab_f, *btab_f, *ctab_f;
     double *atab_d, *btab_d;
     int nlanes;
     Lane lane[kMaxLanes];
@@ -138,6 +140,7 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     helm_hierarchy *Hp = H ? H : &dummy;
     for (int l = 0; l < 3; ++l) {
         Hp->vel[l] = c.take<float>(g[l].nn);
+        Hp->svel[l] = (o.precision == HELM_FP64) ? nullptr : c.take<float>(g[l].nn);
         for (int sh = 0; sh < 2; ++sh) Hp->dinv[l][sh] = vec(l);
         for (int a = 0; a < 3; ++a) {
             Hp->wf[l][a] = c.take<float>(6 * (size_t)(g[l].n[a] + 1));
@@ -146,6 +149,7 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     }
     Hp->atab_f = c.take<float>(20 * (size_t)K);
     Hp->btab_f = c.take<float>(12 * (size_t)K);
+    Hp->ctab_f = c.take<float>(24 * (size_t)(K + 1));
     Hp->atab_d = c.take<double>(20 * (size_t)K);
     Hp->btab_d = c.take<double>(12 * (size_t)K);
     const int nl = (o.lanes > 1) ? o.lanes : 1;
@@ -246,6 +250,50 @@ void hermite_monomials(const double *tab, int K, int f0, int nf, std::vector<dou
         }
 }
 
+// The unshifted shell coefficients (eq. iofd-shell-coefficients with mu = 1) as quintics in
+// the local coordinate t of each table interval: with a_j(t) the cubic Hermite pieces (monomial
+// form `at`, K intervals) and kappa^2 = (2 pi deta (k + t))^2,
+//   C_0 = 6 a4 - kappa^2 a1,  C_1 = a5 - a4 - kappa^2 a2 / 6,
+//   C_2 = (1 - a4 - a5) / 2 - a5 / 2 - kappa^2 a3 / 12,
+//   C_3 = -3 (1 - a4 - a5) / 4 - kappa^2 (1 - a1 - a2 - a3) / 8;
+// interval K is the clamped range eta* = 0.4 (a_j at the last node, s = K + t).
+void shell_quintics(const std::vector<double> &at, int K, std::vector<double> &out) {
+    out.assign((size_t)(K + 1) * 24, 0.0);
+    const double w = 2.0 * M_PI * 0.4 / K;
+    for (int k = 0; k <= K; ++k) {
+        double a[5][4];   // a_j as cubics in t
+        for (int j = 0; j < 5; ++j)
+            for (int d = 0; d < 4; ++d) {
+                if (k < K) {
+                    a[j][d] = at[((size_t)k * 5 + j) * 4 + d];
+                } else {   // value at the end of the last interval, constant in t
+                    const double *p = &at[((size_t)(K - 1) * 5 + j) * 4];
+                    a[j][d] = d == 0 ? p[0] + p[1] + p[2] + p[3] : 0.0;
+                }
+            }
+        const double k2[3] = {w * w * k * k, 2.0 * w * w * k, w * w};   // kappa^2 in t
+        double stiff[4][4] = {}, mass[4][4] = {};
+        for (int d = 0; d < 4; ++d) {
+            const double q = (d == 0 ? 1.0 : 0.0) - a[3][d] - a[4][d];
+            stiff[0][d] = 6.0 * a[3][d];
+            stiff[1][d] = a[4][d] - a[3][d];
+            stiff[2][d] = 0.5 * q - 0.5 * a[4][d];
+            stiff[3][d] = -0.75 * q;
+            mass[0][d] = a[0][d];
+            mass[1][d] = a[1][d] / 6.0;
+            mass[2][d] = a[2][d] / 12.0;
+            mass[3][d] = ((d == 0 ? 1.0 : 0.0) - a[0][d] - a[1][d] - a[2][d]) / 8.0;
+        }
+        for (int m = 0; m < 4; ++m) {
+            double *c = &out[((size_t)k * 4 + m) * 6];
+            for (int d = 0; d < 4; ++d) {
+                c[d] += stiff[m][d];
+                for (int e = 0; e < 3; ++e) c[d + e] -= k2[e] * mass[m][d];
+            }
+        }
+    }
+}
+
 template <typename R>
 void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, const R *wy, const R *wz, const R *at,
                      const R *bt) {
@@ -275,6 +323,10 @@ void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, con
     // FP64 outer residual and Q_h, which do not use it)
     const bool own = (sizeof(R) == sizeof(double)) == (H->prec == HELM_FP64);
     for (int sh = 0; sh < 2; ++sh) L.dinv[sh] = own ? static_cast<const R *>(H->dinv[l][sh]) : nullptr;
+    const bool fp32 = sizeof(R) == sizeof(float) && H->prec != HELM_FP64;
+    L.s = fp32 ? H->svel[l] : nullptr;
+    L.ctab = fp32 ? reinterpret_cast<const R *>(H->ctab_f) : nullptr;
+    L.kap_s = (R)(2.0 * M_PI * 0.4 / H->opt.iofd_K);
 }
 
 // ---------------------------------------------------------------------------
@@ -458,12 +510,14 @@ struct Eng {
     }
 
     // Outer FGMRES(m_out) for one right-hand side (Sec. 3.3); x and b in FP64:
-    // b = Q_h f, solve A_h v = b, u = Q_h v (u may be null: v stays in x64).
-    helm_status solve_one(const T *f, T *u, double tol, int *iters, double *relres) {
+    // b = Q_h f, solve A_h v = b, u = Q_h v (u may be null: v stays in x64);
+    // v_out (optional) receives a copy of v.
+    helm_status solve_one(const T *f, T *u, double tol, int *iters, double *relres, c64 *v_out = nullptr) {
         HIP_TRY((launch_qapply<double, T, c64>(H->Ld[0], f, Ln->b64, s)));   // b = Q_h f
         const helm_status status = solve_b64(tol, iters, relres);
         if (status < 0) return status;
         if (u) HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], Ln->x64, u, s)));   // u = Q_h v
+        if (v_out) HIP_TRY((launch_convert<c64, c64>(Ln->x64, v_out, nn(0), s)));
         HIP_TRY(hipStreamSynchronize(s));
         return status;
     }
@@ -690,6 +744,18 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     return err;
 }
 
+// Tile choices already timed in this process, per device, precision, level shape and
+// kernel family (and the options that restrict the candidates): a later setup of the
+// same shape reuses them instead of timing again.
+struct TileKey {
+    int dev, prec, fam, tz_opt, split_opt, n[3];
+    bool operator<(const TileKey &o) const {
+        return std::memcmp(this, &o, sizeof(TileKey)) < 0;
+    }
+};
+std::mutex g_tile_mutex;
+std::map<TileKey, std::pair<int, int>> g_tile_cache;
+
 hipError_t tune_tiles(helm_hierarchy *H) {
     if (H->opt.tile_tz != 0 && H->opt.tile_split >= 0) {
         for (int l = 0; l < 3; ++l)
@@ -699,10 +765,31 @@ hipError_t tune_tiles(helm_hierarchy *H) {
             }
         return hipSuccess;
     }
+    int dev = 0;
+    HIP_CHK(hipGetDevice(&dev));
     for (int l = 0; l < 3; ++l)
         for (int f = 0; f < 2; ++f) {
+            TileKey key;
+            std::memset(&key, 0, sizeof(key));
+            key.dev = dev;
+            key.prec = H->prec;
+            key.fam = f;
+            key.tz_opt = H->opt.tile_tz;
+            key.split_opt = H->opt.tile_split;
+            for (int a = 0; a < 3; ++a) key.n[a] = H->geom[l].n[a];
+            {
+                std::lock_guard<std::mutex> lock(g_tile_mutex);
+                auto it = g_tile_cache.find(key);
+                if (it != g_tile_cache.end()) {
+                    H->Lf[l].tz[f] = H->Ld[l].tz[f] = it->second.first;
+                    H->Lf[l].split[f] = H->Ld[l].split[f] = it->second.second;
+                    continue;
+                }
+            }
             hipError_t e = (H->prec == HELM_FP64) ? tune_level_tiles<c64>(H, l, f) : tune_level_tiles<c32>(H, l, f);
             if (e != hipSuccess) return e;
+            std::lock_guard<std::mutex> lock(g_tile_mutex);
+            g_tile_cache[key] = {H->Lf[l].tz[f], H->Lf[l].split[f]};
         }
     return hipSuccess;
 }
@@ -832,10 +919,21 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
         if ((e = launch_extend_velocity(velocity, H->nphys, n_pml, 1 << l, g, H->vel[l], s)) != hipSuccess)
             return bail(HELM_EHIP, hipGetErrorString(e));
     }
-    std::vector<double> at, bt;
+    std::vector<double> at, bt, ct;
     hermite_monomials(opt->iofd_table, opt->iofd_K, 0, 5, at);
     hermite_monomials(opt->iofd_table, opt->iofd_K, 5, 3, bt);
-    std::vector<float> atf(at.begin(), at.end()), btf(bt.begin(), bt.end());
+    shell_quintics(at, opt->iofd_K, ct);
+    std::vector<float> atf(at.begin(), at.end()), btf(bt.begin(), bt.end()), ctf(ct.begin(), ct.end());
+    if (H->prec != HELM_FP64) {
+        if ((e = hipMemcpyAsync(H->ctab_f, ctf.data(), ctf.size() * sizeof(float), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return bail(HELM_EHIP, std::string("table upload: ") + hipGetErrorString(e));
+        for (int l = 0; l < 3; ++l) {
+            const double factor = omega * H->geom[l].ell * opt->iofd_K / (0.4 * 2.0 * M_PI);
+            if ((e = launch_scaled_eta(H->vel[l], H->geom[l].nn, factor, H->svel[l], s)) != hipSuccess)
+                return bail(HELM_EHIP, hipGetErrorString(e));
+        }
+    }
     if ((e = hipMemcpyAsync(H->atab_d, at.data(), at.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(H->btab_d, bt.data(), bt.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(H->atab_f, atf.data(), atf.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -857,19 +955,21 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
     return HELM_OK;
 }
 
-helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, int *iters, double *relres) {
+static helm_status solve_impl(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, void *v, int *iters,
+                              double *relres) {
     if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
     if (!f || !u || !iters || !relres || nrhs < 0 || !(tol > 0) || !std::isfinite(tol))
         return fail(H, HELM_EINVAL, "invalid solve arguments");
-    if (f == u) return fail(H, HELM_EINVAL, "f and u must not alias");
+    if (f == u || v == f || v == u) return fail(H, HELM_EINVAL, "f, u and v must not alias");
     const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
     const long long n = H->geom[0].nn;
     auto one = [&](int lane, int r) {
         const char *fr = static_cast<const char *>(f) + (size_t)r * n * es;
         char *ur = static_cast<char *>(u) + (size_t)r * n * es;
+        c64 *vr = v ? static_cast<c64 *>(v) + (size_t)r * n : nullptr;
         return (H->prec == HELM_FP64)
-                   ? Eng<c64>(H, lane).solve_one((const c64 *)fr, (c64 *)ur, tol, iters + r, relres + r)
-                   : Eng<c32>(H, lane).solve_one((const c32 *)fr, (c32 *)ur, tol, iters + r, relres + r);
+                   ? Eng<c64>(H, lane).solve_one((const c64 *)fr, (c64 *)ur, tol, iters + r, relres + r, vr)
+                   : Eng<c32>(H, lane).solve_one((const c32 *)fr, (c32 *)ur, tol, iters + r, relres + r, vr);
     };
     const int L = std::min(H->nlanes, nrhs);
     if (L <= 1) {
@@ -923,6 +1023,16 @@ helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, v
     return worst;
 }
 
+helm_status helm_solve(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, int *iters, double *relres) {
+    return solve_impl(H, f, nrhs, tol, u, nullptr, iters, relres);
+}
+
+helm_status helm_solve_checkpoint(helm_hierarchy *H, const void *f, int nrhs, double tol, void *u, void *v, int *iters,
+                                  double *relres) {
+    if (!v) return fail(H, HELM_EINVAL, "v must not be NULL");
+    return solve_impl(H, f, nrhs, tol, u, v, iters, relres);
+}
+
 // Gradient workspace: v (c64), the adjoint residual (c64), the FP64 per-node sums, one
 // working-precision vector and the per-axis PML node factors 1/xi (c64).
 static size_t grad_ws_bytes(const helm_hierarchy *H) {
@@ -940,8 +1050,8 @@ helm_status helm_grad_workspace_size(const helm_hierarchy *H, size_t *bytes) {
     return HELM_OK;
 }
 
-helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int nrhs, double tol, float *grad_m,
-                      void *workspace, size_t ws_bytes, int *iters, double *relres) {
+helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, const void *v_fwd, int nrhs, double tol,
+                      float *grad_m, void *workspace, size_t ws_bytes, int *iters, double *relres) {
     if (!H) return fail(nullptr, HELM_EINVAL, "hierarchy is NULL");
     if (!f || !adj_src || !grad_m || !workspace || !iters || !relres || nrhs < 1 || !(tol > 0) ||
         !std::isfinite(tol))
@@ -986,11 +1096,20 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
         for (int r = 0; r < nrhs; ++r) {
             const TT *fr = reinterpret_cast<const TT *>(static_cast<const char *>(f) + (size_t)r * n * es);
             const TT *sr = reinterpret_cast<const TT *>(static_cast<const char *>(adj_src) + (size_t)r * n * es);
-            // forward: A_h v = Q_h f (v kept in FP64)
-            helm_status st = E.solve_one(fr, nullptr, tol, iters + 2 * r, relres + 2 * r);
-            if (st < 0) return st;
-            if (st == HELM_NOT_CONVERGED) worst = st;
-            HIP_TRY((launch_convert<c64, c64>(E.Ln->x64, v64, n, E.s)));
+            const c64 *vr = v64;
+            helm_status st = HELM_OK;
+            if (v_fwd) {
+                // checkpointed forward solution (helm_solve_checkpoint): no forward solve
+                vr = static_cast<const c64 *>(v_fwd) + (size_t)r * n;
+                iters[2 * r] = 0;
+                relres[2 * r] = 0.0;
+            } else {
+                // forward: A_h v = Q_h f (v kept in FP64)
+                st = E.solve_one(fr, nullptr, tol, iters + 2 * r, relres + 2 * r);
+                if (st < 0) return st;
+                if (st == HELM_NOT_CONVERGED) worst = st;
+                HIP_TRY((launch_convert<c64, c64>(E.Ln->x64, v64, n, E.s)));
+            }
             // adjoint: A_h^T mu = Q_h^T conj(s)
             HIP_TRY((launch_qapply_t<double, TT, c64>(H->Ld[0], sr, true, E.Ln->b64, E.s)));
             E.transposed = true;
@@ -1001,7 +1120,7 @@ helm_status helm_grad(helm_hierarchy *H, const void *f, const void *adj_src, int
             E.transposed = false;
             if (st < 0) return st;
             if (st == HELM_NOT_CONVERGED) worst = st;
-            HIP_TRY((launch_grad_node<TT>(H->Ld[0], v64, E.Ln->x64, sr, fr, gacc, E.s)));
+            HIP_TRY((launch_grad_node<TT>(H->Ld[0], vr, E.Ln->x64, sr, fr, gacc, E.s)));
         }
         HIP_TRY(launch_grad_phys(gacc, H->geom[0], H->n_pml, H->nphys, grad_m, E.s));
         HIP_TRY(hipStreamSynchronize(E.s));

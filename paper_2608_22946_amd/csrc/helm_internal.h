@@ -72,6 +72,15 @@ struct LevelArgs {
     int tz[2];           // z planes per wavefront (0: default rule)
     int split[2];        // 1: an interior launch plus a border launch where the tiling allows
     const R *dinv[2];    // per node D^-1 of A_l ([0]) and B_l ([1]), complex interleaved; 0 on the boundary
+    // FP32 levels: the interpolation coordinate before the clamp at eta* = 0.4, per node,
+    // s = omega ell K / (0.4 * 2 pi c) (formed in FP64 at setup), read instead of c by the
+    // stencils: eta* = min(s, K) 0.4 / K and kappa = s kap_s, without a reciprocal per node;
+    // and the unshifted shell coefficients C_0..C_3 (eq. iofd-shell-coefficients, mu = 1) as
+    // quintics in the local coordinate t of each table interval, interval K standing for
+    // the clamped range s >= K (t = s - K unbounded there).  Null in FP64 arguments.
+    const float *s;
+    const R *ctab;       // [K + 1][4][6] monomial coefficients in t
+    R kap_s;             // kappa per unit of s: 0.4 * 2 pi / K
 };
 
 // ---------------------------------------------------------------------------
@@ -215,6 +224,8 @@ hipError_t launch_convert(const TI *x, TO *y, long long n, hipStream_t s);
 
 hipError_t launch_extend_velocity(const float *phys, const int nphys[3], int n_pml, int stride_fine,
                                   const Geom &g, float *out, hipStream_t s);
+// out_i = factor / c_i in FP64, rounded to FP32 (the scaled interpolation coordinate s of LevelArgs)
+hipError_t launch_scaled_eta(const float *c, long long n, double factor, float *out, hipStream_t s);
 
 hipError_t launch_velocity_check(const float *v, long long n, const RedBuf &rb, double *out, hipStream_t s);
 

@@ -105,12 +105,35 @@ __device__ __forceinline__ void locate(const LevelArgs<R> &L, float c, R &kappa,
 
 template <typename R>
 __device__ __forceinline__ R horner(const R *p, R t) { return ((p[3] * t + p[2]) * t + p[1]) * t + p[0]; }
+template <typename R>
+__device__ __forceinline__ R horner5(const R *p, R t) {
+    return ((((p[5] * t + p[4]) * t + p[3]) * t + p[2]) * t + p[1]) * t + p[0];
+}
+
+// FP32 levels read the scaled coordinate s = omega ell K / (0.4 * 2 pi c) per node instead of
+// c (LevelArgs::s): the same interval and local coordinate as `locate`, and kappa = s kap_s.
+template <typename R>
+constexpr bool scaled_coordinate() { return sizeof(R) == sizeof(float); }
 
 template <typename R>
-__device__ __forceinline__ Coef<R> coef_at(const LevelArgs<R> &L, const R *stab, float c) {
+__device__ __forceinline__ void locate_s(const LevelArgs<R> &L, float s, R &kappa, int &k, R &t) {
+    kappa = (R)s * L.kap_s;
+    const R u = (R)s < (R)L.K ? (R)s : (R)L.K;   // eta* clamped at 0.4
+    k = (int)u;
+    k = k < L.K - 1 ? k : L.K - 1;
+    t = u - (R)k;
+}
+
+// the five coefficient functions and kappa^2 at a node; v is the per-node value the level
+// stores (s on FP32 levels, the velocity c on FP64 ones)
+template <typename R>
+__device__ __forceinline__ Coef<R> coef_at(const LevelArgs<R> &L, const R *stab, float v) {
     R kappa, t;
     int k;
-    locate(L, c, kappa, k, t);
+    if (scaled_coordinate<R>())
+        locate_s(L, v, kappa, k, t);
+    else
+        locate(L, v, kappa, k, t);
     const R *p = stab + k * 20;
     Coef<R> o;
     o.a1 = horner(p + 0, t);
@@ -120,6 +143,27 @@ __device__ __forceinline__ Coef<R> coef_at(const LevelArgs<R> &L, const R *stab,
     o.a5 = horner(p + 16, t);
     o.k2 = kappa * kappa;
     return o;
+}
+
+// unshifted shell coefficients C_0..C_3 at a node of an FP32 level from the quintic table
+// (LDS copy `ctab`): interval min(floor(s), K), the last one unbounded in t
+template <typename R>
+__device__ __forceinline__ void shell_at_s(const LevelArgs<R> &L, const R *ctab, float s, R &c0, R &c1, R &c2,
+                                           R &c3) {
+    int k = (int)s;
+    k = k < L.K ? k : L.K;
+    const R t = (R)s - (R)k;
+    const R *p = ctab + k * 24;
+    c0 = horner5(p, t);
+    c1 = horner5(p + 6, t);
+    c2 = horner5(p + 12, t);
+    c3 = horner5(p + 18, t);
+}
+
+// per-node value a level's coefficient evaluation reads
+template <typename R>
+__device__ __forceinline__ const float *node_values(const LevelArgs<R> &L) {
+    return scaled_coordinate<R>() ? L.s : L.c;
 }
 
 // diagonal entry ell^2 D = a4 (wxc + wyc + wzc) - mu kappa^2 a1
@@ -138,7 +182,7 @@ struct Plane {
     Z<R> gc;           // right-hand side at the centre (residual / Jacobi modes)
     Z<R> dc;           // D^-1 at the centre (Jacobi modes)
     Z<R> bc;           // base value at the centre (fused Jacobi + base)
-    float cc;          // velocity at the centre
+    float cc;          // per-node value at the centre (s on FP32 levels, c on FP64 ones)
 };
 
 // In-plane partial sums of one z plane from the rows y-1 (a), y (b), y+1 (c)
@@ -187,15 +231,28 @@ __device__ __forceinline__ void plane_partials(Z<R> a, Z<R> b, Z<R> c, const Z<R
     P.eb = eb;
 }
 
-// ell^2 (H v) at the centre of plane "o" from planes m (z-1), o (z), p (z+1)
+// H v at the centre of plane "o" from planes m (z-1), o (z), p (z+1); the row's coefficients
+// come from the per-node value o.cc (s or c).  Unshifted rows of an FP32 level free of
+// stretching take the shell coefficients from the quintic table (one Horner per
+// coefficient); every other row evaluates alpha_1..alpha_5 (eq. iofd-shell-coefficients,
+// or the tensor-product form in the PML).
 template <typename R, bool XYI, bool SHIFT>
-__device__ __forceinline__ Z<R> row_value(const LevelArgs<R> &L, const Coef<R> &cf, const Plane<R> &m,
+__device__ __forceinline__ Z<R> row_value(const LevelArgs<R> &L, const R *stab, const R *ctab, const Plane<R> &m,
                                           const Plane<R> &o, const Plane<R> &p, bool zint, const Z<R> *wz) {
     // shell sums S_m over the 1 / 6 / 12 / 8 neighbours
     const Z<R> S0 = o.p0;
     const Z<R> S1 = zadd(o.p1, zadd(m.p0, p.p0));
     const Z<R> S2 = zadd(o.p2, zadd(m.p1, p.p1));
     const Z<R> S3 = zadd(m.p2, p.p2);
+    if (scaled_coordinate<R>() && !SHIFT && XYI && zint) {
+        R c0, c1, c2, c3;
+        shell_at_s(L, ctab, o.cc, c0, c1, c2, c3);
+        Z<R> out;
+        out.r = c0 * S0.r + c1 * S1.r + c2 * S2.r + c3 * S3.r;
+        out.i = c0 * S0.i + c1 * S1.i + c2 * S2.i + c3 * S3.i;
+        return zscale(L.inv_ell2, out);
+    }
+    const Coef<R> cf = coef_at(L, stab, o.cc);
     const R a1 = cf.a1, a2 = cf.a2, a3 = cf.a3, a4 = cf.a4, a5 = cf.a5;
     const R q = (R)1 - a4 - a5;
     const R m0 = a1, m1 = a2 * (R)(1.0 / 6), m2 = a3 * (R)(1.0 / 12), m3 = ((R)1 - a1 - a2 - a3) * (R)0.125;
@@ -387,10 +444,11 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
     // outstanding loads the same on every path through the loop, so waiting
     // for one plane never waits for the planes issued after it.
     const int zlast = min(z1, L.nz);
+    const float *vnode = node_values(L);
     auto issue = [&](int zp, Raw &r) {
         const int zc = min(max(zp, 0), zlast);
         r.zp = zp;
-        const float *cp = plane_ptr(L.c, L.sy, zc);
+        const float *cp = plane_ptr(vnode, L.sy, zc);
         r.cb = at_byte(cp, bc0);
         if (!JAC) {
             const TX *xp = plane_ptr(x, L.sy, zc);
@@ -448,11 +506,10 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
         Z<R> res = zero;
         const bool interior = x_int && yint && z >= 1 && z <= L.nz - 1;
         if (interior) {
-            const Coef<R> cf = coef_at(L, stab, o.cc);
             const bool zint = (z >= L.loz && z <= L.hiz);
             const R *wzp = L.wz + 6 * z;
             const Z<R> wz[3] = {{wzp[0], wzp[1]}, {wzp[2], wzp[3]}, {wzp[4], wzp[5]}};
-            const Z<R> Hv = row_value<R, XI && YI, SHIFT>(L, cf, m, o, p, zint, wz);
+            const Z<R> Hv = row_value<R, XI && YI, SHIFT>(L, stab, stab + 20 * L.K, m, o, p, zint, wz);
             if (MODE == M_APPLY) {
                 res = Hv;
             } else if (MODE == M_RESID || RESTRICT) {
@@ -560,9 +617,11 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
                                                  const TY *__restrict__ base, TY *__restrict__ y, R omegaJ, TileMap M,
                                                  RedBuf rb, KState *st) {
     extern __shared__ unsigned char smem_raw[];
-    R *stab = reinterpret_cast<R *>(smem_raw);
+    R *stab = reinterpret_cast<R *>(smem_raw);   // alpha pieces, then (FP32) the shell quintics
     const int tid = threadIdx.x + 64 * threadIdx.y;
     for (int i = tid; i < L.K * 20; i += 256) stab[i] = L.atab[i];
+    if (scaled_coordinate<R>())
+        for (int i = tid; i < (L.K + 1) * 24; i += 256) stab[L.K * 20 + i] = L.ctab[i];
     __syncthreads();
 
     // XCD-aware tile order: block b runs on XCD b % 8; give each XCD a contiguous tile range
@@ -730,7 +789,7 @@ __global__ void __launch_bounds__(256) k_diag(LevelArgs<R> L, const T *__restric
         const int zi = (int)(i / L.sy);
         Z<R> r = {0, 0};
         if (xi >= 1 && xi <= L.nx - 1 && yi >= 1 && yi <= L.ny - 1 && zi >= 1 && zi <= L.nz - 1) {
-            Coef<R> cf = coef_at(L, stab, L.c[i]);
+            Coef<R> cf = coef_at(L, stab, node_values(L)[i]);
             Z<R> ws = {L.wx[6 * xi + 2] + L.wy[6 * yi + 2] + L.wz[6 * zi + 2],
                        L.wx[6 * xi + 3] + L.wy[6 * yi + 3] + L.wz[6 * zi + 3]};
             r = zmul(diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, ws), ld<R>(x, i));
@@ -771,7 +830,7 @@ __global__ void __launch_bounds__(256) k_dinv(LevelArgs<R> L, R *__restrict__ ou
         const int zi = (int)(i / L.sy);
         Z<R> r = {0, 0};
         if (xi >= 1 && xi <= L.nx - 1 && yi >= 1 && yi <= L.ny - 1 && zi >= 1 && zi <= L.nz - 1) {
-            Coef<R> cf = coef_at(L, stab, L.c[i]);
+            Coef<R> cf = coef_at(L, stab, node_values(L)[i]);
             Z<R> ws = {L.wx[6 * xi + 2] + L.wy[6 * yi + 2] + L.wz[6 * zi + 2],
                        L.wx[6 * xi + 3] + L.wy[6 * yi + 3] + L.wz[6 * zi + 3]};
             r = zdiv(Z<R>{1, 0}, diag_of<R, SHIFT>(L, cf.a1, cf.a4, cf.k2, ws));
@@ -795,7 +854,7 @@ template <typename R, typename TX, typename TG, typename TY, int PART>
 hipError_t launch_stencil_part(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, const TileMap &M,
                                int blocks, hipStream_t s) {
     const dim3 blk(64, kWavesY);
-    const size_t shm = sizeof(R) * L.K * 20;
+    const size_t shm = sizeof(R) * (L.K * 20 + (scaled_coordinate<R>() ? (L.K + 1) * 24 : 0));
     const TX *x = (const TX *)c.x;
     const TG *g = (const TG *)c.g;
     const TY *base = (const TY *)c.base;
@@ -844,6 +903,7 @@ hipError_t launch_stencil_part(const LevelArgs<R> &L, const StencilCall &c, cons
 
 template <typename R, typename TX, typename TG, typename TY>
 hipError_t launch_stencil(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, hipStream_t s) {
+    if (scaled_coordinate<R>() && (!L.s || !L.ctab)) return hipErrorInvalidValue;   // FP32 levels read s
     // the Jacobi modes read the stored D^-1 of the operator
     if ((c.mode == M_JSWEEP || c.mode == M_JAC2 || c.mode == M_JAC2_ADD) && !L.dinv[c.shifted ? 1 : 0])
         return hipErrorInvalidValue;

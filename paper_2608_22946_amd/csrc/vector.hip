@@ -533,6 +533,12 @@ __global__ void __launch_bounds__(256) k_extend_velocity(const float *__restrict
     }
 }
 
+__global__ void __launch_bounds__(256) k_scaled_eta(const float *__restrict__ c, long long n, double factor,
+                                                   float *__restrict__ out) {
+    const long long i = elem_index();
+    if (i < n) out[i] = (float)(factor / (double)c[i]);
+}
+
 // min, max and the count of non-finite values of the velocity
 __global__ void __launch_bounds__(256) k_velocity_check(const float *__restrict__ v, long long n, RedBuf rb,
                                                        double *out) {
@@ -751,6 +757,11 @@ hipError_t launch_extend_velocity(const float *phys, const int nphys[3], int n_p
                                   float *out, hipStream_t s) {
     hipLaunchKernelGGL(k_extend_velocity, dim3(stream_blocks(g.nn)), dim3(256), 0, s, phys, nphys[0], nphys[1],
                        nphys[2], n_pml, stride, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scaled_eta(const float *c, long long n, double factor, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_scaled_eta, dim3(stream_blocks(n)), dim3(256), 0, s, c, n, factor, out);
     return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@ class HelmOptions(ctypes.Structure):
                 ("tile_tz", _c_int), ("tile_split", _c_int), ("lanes", _c_int)]
 
 
-EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_grad",
+EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_solve_checkpoint",
+            "helm_grad",
             "helm_grad_workspace_size", "helm_grad_to_velocity", "helm_destroy",
             "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_residual_restrict", "helm_jacobi",
             "helm_restrict",
@@ -57,7 +58,8 @@ def lib():
         L.helm_workspace_size.argtypes = [I, I, I, I, ctypes.POINTER(HelmOptions), ctypes.POINTER(_c_size_t)]
         L.helm_setup.argtypes = [P, I, I, I, D, D, I, ctypes.POINTER(HelmOptions), P, _c_size_t, ctypes.POINTER(P)]
         L.helm_solve.argtypes = [P, P, I, D, P, P, P]
-        L.helm_grad.argtypes = [P, P, P, I, D, P, P, _c_size_t, P, P]
+        L.helm_solve_checkpoint.argtypes = [P, P, I, D, P, P, P, P]
+        L.helm_grad.argtypes = [P, P, P, P, I, D, P, P, _c_size_t, P, P]
         L.helm_grad_workspace_size.argtypes = [P, ctypes.POINTER(_c_size_t)]
         L.helm_grad_to_velocity.argtypes = [P, P, P]
         L.helm_destroy.argtypes = [P]
@@ -264,11 +266,13 @@ class Hierarchy:
         c = out[0::2] + 1j * out[1::2]
         return c[:k], c[k].real
 
-    def grad(self, f, adj_src, tol):
+    def grad(self, f, adj_src, tol, v=None):
         """dJ/dm (m = 1/c^2) at the physical nodes for sources f and adjoint sources s
         (dJ = Re sum conj(s) du, u = Q v, A v = Q f); f and s of shape (nrhs, ...) or a
-        single grid function.  Returns (float32 gradient on the physical grid, forward
-        and adjoint preconditioner calls [nrhs, 2], true relative residuals [nrhs, 2], rc)."""
+        single grid function; v (optional, complex128, same leading shape): the forward
+        solutions from solve_checkpoint, which skips the forward solves.  Returns (float32
+        gradient on the physical grid, forward and adjoint preconditioner calls [nrhs, 2],
+        true relative residuals [nrhs, 2], rc)."""
         single = f.dim() == 3
         fb = f.unsqueeze(0) if single else f
         sb = adj_src.unsqueeze(0) if single else adj_src
@@ -278,6 +282,12 @@ class Hierarchy:
                 raise ValueError("sources must be contiguous with the level-0 shape and precision dtype")
         if fb.shape != sb.shape:
             raise ValueError("f and adj_src must have the same shape")
+        vp = None
+        if v is not None:
+            vb = v.unsqueeze(0) if v.dim() == 3 else v
+            if vb.dtype != torch.complex128 or vb.shape != fb.shape or not vb.is_contiguous() or vb.device != self.device:
+                raise ValueError("v must be a contiguous complex128 tensor shaped like f")
+            vp = _ptr(vb)
         nrhs = fb.shape[0]
         nbytes = _c_size_t(0)
         _check(lib().helm_grad_workspace_size(self._h, ctypes.byref(nbytes)), self._h)
@@ -287,7 +297,7 @@ class Hierarchy:
         g = torch.empty((nz + 1, ny + 1, nx + 1), dtype=torch.float32, device=self.device)
         its = np.zeros((nrhs, 2), np.int32)
         rel = np.zeros((nrhs, 2), np.float64)
-        rc = lib().helm_grad(self._h, _ptr(fb), _ptr(sb), nrhs, float(tol), _ptr(g), _c_void_p(ws_ptr),
+        rc = lib().helm_grad(self._h, _ptr(fb), _ptr(sb), vp, nrhs, float(tol), _ptr(g), _c_void_p(ws_ptr),
                              nbytes.value, its.ctypes.data, rel.ctypes.data)
         _check(rc, self._h, allow_not_converged=True)
         return g, its, rel, rc
@@ -297,6 +307,26 @@ class Hierarchy:
         g = torch.empty_like(grad_m) if out is None else out
         _check(lib().helm_grad_to_velocity(self._h, _ptr(grad_m), _ptr(g)), self._h)
         return g
+
+    def solve_checkpoint(self, f, tol, out=None, v_out=None):
+        """solve() that also returns the FP64 forward solutions v (A v = Q f) for grad(v=...)."""
+        single = f.dim() == 3
+        fb = f.unsqueeze(0) if single else f
+        if fb.dtype != self.cdtype or tuple(fb.shape[1:]) != self.shape(0) or not fb.is_contiguous():
+            raise ValueError("right-hand sides must be contiguous with the level-0 shape and precision dtype")
+        nrhs = fb.shape[0]
+        u = torch.empty_like(fb) if out is None else out
+        v = torch.empty(fb.shape, dtype=torch.complex128, device=self.device) if v_out is None else v_out
+        if v.dtype != torch.complex128 or v.shape != fb.shape or not v.is_contiguous():
+            raise ValueError("v_out must be a contiguous complex128 tensor shaped like f")
+        its = np.zeros(nrhs, np.int32)
+        rel = np.zeros(nrhs, np.float64)
+        rc = lib().helm_solve_checkpoint(self._h, _ptr(fb), nrhs, float(tol), _ptr(u), _ptr(v), its.ctypes.data,
+                                         rel.ctypes.data)
+        _check(rc, self._h, allow_not_converged=True)
+        if single:
+            return u[0], v[0], int(its[0]), float(rel[0]), rc
+        return u, v, its, rel, rc
 
     def solve(self, f, tol, out=None):
         """u = Q v with A v = Q f; f of shape (nrhs, ...) or a single grid function."""
@@ -344,15 +374,15 @@ class _Solve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vel, f, h, omega, n_pml, tol, kwargs):
         hier = Hierarchy(vel.detach(), h, omega, n_pml, device=f.device, **kwargs)
-        u, its, rel, rc = hier.solve(f, tol)
+        u, v, its, rel, rc = hier.solve_checkpoint(f, tol)
         ctx.hier, ctx.tol = hier, tol
-        ctx.save_for_backward(f)
+        ctx.save_for_backward(f, v)          # checkpointed forward solution: no second forward solve
         return u
 
     @staticmethod
     def backward(ctx, gu):
-        (f,) = ctx.saved_tensors
-        gm, its, rel, rc = ctx.hier.grad(f, gu.to(f.dtype).contiguous(), ctx.tol)
+        f, v = ctx.saved_tensors
+        gm, its, rel, rc = ctx.hier.grad(f, gu.to(f.dtype).contiguous(), ctx.tol, v=v)
         gc = ctx.hier.grad_to_velocity(gm)
         return gc, None, None, None, None, None, None
 

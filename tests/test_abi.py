@@ -134,7 +134,8 @@ def test_calls_on_null_hierarchy(L):
     assert L.helm_solve(None, ctypes.c_void_p(8), 1, 1e-6, ctypes.c_void_p(16), its.ctypes.data, rel.ctypes.data) == -1
     assert L.helm_apply(None, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(16)) == -1
     assert L.helm_residual_restrict(None, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(24)) == -1
-    assert L.helm_grad(None, None, None, 1, 1e-6, None, None, 0, None, None) == -1
+    assert L.helm_grad(None, None, None, None, 1, 1e-6, None, None, 0, None, None) == -1
+    assert L.helm_solve_checkpoint(None, None, 1, 1e-6, None, None, None, None) == -1
     nb = ctypes.c_size_t(0)
     assert L.helm_grad_workspace_size(None, ctypes.byref(nb)) == -1
     L.helm_destroy(None)

@@ -4,6 +4,17 @@ oracle on the same seeded inputs.
 Bars: FP64 stencil-type kernels <= 1e-12 relative L2, FP32 <= 1e-6; nested
 Krylov maps in FP64 within the rounding amplification of their small dense
 solves (stated per test); converged solutions <= 1e-5.
+
+FP32 nested maps (C_4h, V^sigma_2h, K_2h, S_h, Algorithm 1) <= FP32_MAP_GATE =
+1e-5 against the FP64 oracle.  Derivation: the oracle measures each map's
+relative output change per relative input change at the FP32 unit roundoff
+u = 2^-24 on the test grid as at most 1.05 (a random input perturbation of
+size u moves C_4h by 1.005 u, V^sigma_2h by 1.000 u, K_2h by 1.000 u, S_h by
+0.998 u and Algorithm 1 by 1.043 u), so FP32 rounding is not amplified by the
+maps; each map composes at most ~400 FP32-rounded stencil and vector passes
+(K_2h: 2 cycles x 10 steps x a V-cycle of ~20 passes), each contributing at
+most ~5 u of uncorrelated relative error, which random-walks to
+sqrt(400) x 5 u x 1.05 = 6.3e-6 <= 1e-5.  Measured: 1.4e-7 .. 6.2e-7.
 """
 import numpy as np
 import pytest
@@ -15,6 +26,7 @@ from workloads.configs import omega_for_ppw
 pytestmark = pytest.mark.gpu
 
 H = 10.0
+FP32_MAP_GATE = 1e-5
 
 
 def rel(a, b):
@@ -153,21 +165,24 @@ def test_bottom(pair):
     q = pair.rand(2, 201)
     e = to_np(pair.g.bottom(pair.dev(q)))
     err = rel(e, pair.o.bottom(q.astype(complex)))
-    assert err <= pair.tol(1e-9, 2e-3), err
+    print(f"\nbottom {pair.prec}: {err:.3e}")
+    assert err <= pair.tol(1e-9, FP32_MAP_GATE), err
 
 
 def test_vcycle(pair):
     q = pair.rand(1, 202)
     y = to_np(pair.g.vcycle(pair.dev(q)))
     err = rel(y, pair.o.vcycle(q.astype(complex)))
-    assert err <= pair.tol(1e-9, 2e-3), err
+    print(f"\nvcycle {pair.prec}: {err:.3e}")
+    assert err <= pair.tol(1e-9, FP32_MAP_GATE), err
 
 
 def test_coarse_solve(pair):
     r = pair.rand(1, 203)
     e = to_np(pair.g.coarse_solve(pair.dev(r)))
     err = rel(e, pair.o.k2h(r.astype(complex)))
-    assert err <= pair.tol(1e-8, 1e-2), err
+    print(f"\nk2h {pair.prec}: {err:.3e}")
+    assert err <= pair.tol(1e-8, FP32_MAP_GATE), err
 
 
 @pytest.mark.parametrize("x0", [False, True])
@@ -177,7 +192,8 @@ def test_smooth(pair, x0):
     x = to_np(pair.g.smooth(pair.dev(g), pair.dev(xi) if x0 else None))
     ref = pair.o.smooth(g.astype(complex), xi.astype(complex) if x0 else None)
     err = rel(x, ref)
-    assert err <= pair.tol(1e-10, 1e-4), err
+    print(f"\nsmooth {pair.prec} x0={x0}: {err:.3e}")
+    assert err <= pair.tol(1e-10, FP32_MAP_GATE), err
 
 
 @pytest.mark.parametrize("m_h", [1, 3])
@@ -205,14 +221,15 @@ def test_bottom_jacobi_counts(nJ, precision):
     q = p.rand(2, 216)
     e = to_np(p.g.bottom(p.dev(q)))
     err = rel(e, p.o.bottom(q.astype(complex)))
-    assert err <= p.tol(1e-9, 2e-3), err
+    assert err <= p.tol(1e-9, FP32_MAP_GATE), err
 
 
 def test_precond(pair):
     r = pair.rand(0, 206)
     z = to_np(pair.g.precond(pair.dev(r)))
     err = rel(z, pair.o.precond(r.astype(complex)))
-    assert err <= pair.tol(1e-8, 1e-2), err
+    print(f"\nprecond {pair.prec}: {err:.3e}")
+    assert err <= pair.tol(1e-8, FP32_MAP_GATE), err
 
 
 def test_random_table_apply_and_q():
@@ -296,10 +313,10 @@ def test_tiling_smooth_and_precond(tiled):
     p = tiled
     r, x0 = p.rand(0, 440), p.rand(0, 441)
     err = rel(to_np(p.g.smooth(p.dev(r), p.dev(x0))), p.o.smooth(r.astype(complex), x0.astype(complex)))
-    assert err <= p.tol(1e-10, 1e-4), err
+    assert err <= p.tol(1e-10, FP32_MAP_GATE), err
     r = p.rand(0, 442)
     err = rel(to_np(p.g.precond(p.dev(r))), p.o.precond(r.astype(complex)))
-    assert err <= p.tol(1e-8, 1e-2), err
+    assert err <= p.tol(1e-8, FP32_MAP_GATE), err
 
 
 # ---- whole solve ----
@@ -323,8 +340,9 @@ def test_solve_small_config_fp64():
                          ids=["tz4-split", "tz32-one"])
 def test_solve_fixed_tiling_fp32(tiling):
     """FP32 solve with the tiling fixed: the outer restart residual norm runs
-    through the split launches; the answer matches the FP64 oracle's within
-    the spread of two solves stopped at relative residual 1e-6."""
+    through the split launches; the answer is within 1e-5 of the FP64 oracle's
+    converged solution (tol 1e-10).  The oracle stopped at 1e-6 is measured beside
+    it: a 1e-6 residual allows ~5e-7 on this problem in FP64 arithmetic too."""
     n, npml = 44, 10
     vel = grf_velocity(n, n, n, seed=21, corr_len=8.0)
     p = Pair(vel, npml, "fp32", tiling=tiling)
@@ -334,9 +352,13 @@ def test_solve_fixed_tiling_fp32(tiling):
     assert rc == 0 and relres <= 1e-6
     uo, its_o, rel_o, st = p.o.solve(f.astype(complex), 1e-6)
     assert st == 0
-    err = rel(to_np(u), uo)
-    print(f"fixed tiling {tiling}: |u - u_ref| / |u_ref| = {err:.2e}, {its} vs {its_o} preconditioner calls")
-    assert err <= 2e-5, (err, its, its_o)
+    ur, its_r, rel_r, st_r = p.o.solve(f.astype(complex), 1e-10)
+    assert st_r == 0
+    err = rel(to_np(u), ur)
+    print(f"\nfixed tiling {tiling}: |u - u_ref| / |u_ref| = {err:.2e} (oracle at 1e-10); {its} vs {its_o} "
+          f"preconditioner calls to 1e-6; GPU vs oracle at 1e-6 {rel(to_np(u), uo):.2e}, oracle at 1e-6 vs "
+          f"1e-10 {rel(uo, ur):.2e}")
+    assert err <= 1e-5, (err, its, its_o)
 
 
 @pytest.mark.parametrize("lanes", [2, 3])
@@ -360,6 +382,35 @@ def test_solve_lanes_match_one_lane(lanes):
     assert rc1 == 0 and rc2 == 0
     assert list(it1) == list(it2) and np.array_equal(rel1, rel2)
     assert torch.equal(u1, u2)
+
+
+@pytest.mark.parametrize("medium", ["lens", "wedge", "barrier"])
+def test_paper_media_solve_fp64(medium):
+    """The closed-form benchmark media of Sec. 6.2 on a small mesh: 48^3 physical
+    cells + 8 PML (64^3 total), normalised coordinates (physical box [0, 1]^3,
+    h = 1/48), 6 points per wavelength at the minimum velocity, point source at the
+    centre node.  FP64 GPU solve to 1e-8 against the oracle solved to 1e-10, every
+    node.  The barrier (c = 1e10 in a slab) drives eta* to 0 there: kappa^2 vanishes
+    in the mass term and the table is read at its first node."""
+    from workloads import barrier_velocity, lens_velocity, wedge_velocity
+    n, npml = 48, 8
+    h = 1.0 / n
+    vel = {"lens": lens_velocity, "wedge": wedge_velocity, "barrier": barrier_velocity}[medium](n, n, n)
+    from oracle.oracle import Hierarchy as OH
+    from paper_2608_22946_amd import helm
+    table = load_iofd_table()
+    omega = omega_for_ppw(float(vel.min()), h)
+    g = helm.Hierarchy(torch.from_numpy(vel), h, omega, npml, precision="fp64", table=table)
+    o = OH(vel, h, omega, npml, table)
+    N = n + 2 * npml
+    f = point_source((N, N, N), (N // 2,) * 3, h)
+    u, its, relres, rc = g.solve(torch.from_numpy(f).cuda(), 1e-8)
+    assert rc == 0 and relres <= 1e-8
+    uo, its_o, rel_o, st = o.solve(f, 1e-10)
+    assert st == 0
+    err = rel(to_np(u), uo)
+    print(f"\n{medium}: |u_gpu - u_ref|/|u_ref| = {err:.3e}, {its} PC calls (oracle {its_o} to 1e-10)")
+    assert err <= 1e-6, err
 
 
 def test_solve_dense_direct_fp64():
@@ -464,6 +515,36 @@ def test_c2_solve_residual(c2):
     assert true_rel <= 1.2e-6, (true_rel, relres, its)
 
 
+def test_c2_crop_solution_fp32(c2):
+    """Converged-solution parity on the benchmark's own physics: a 64^3-cell crop of
+    the 320^3 GRF velocity (seed 2, correlation length 20 cells, 2000 m/s +-25%
+    clipped to [1500, 3000]) around the benchmark's seeded source, plus 16 PML cells
+    (96^3 total), 6 points per wavelength at the crop's minimum velocity, the
+    derived table (Q_h included).  FP32 GPU solve to 1e-6 against the FP64 oracle
+    solved to 1e-10, every node; the oracle stopped at 1e-6 is measured beside it
+    (the error a 1e-6 residual allows in FP64 arithmetic)."""
+    _, vel = c2
+    n, npml, N = 64, 16, 352
+    rng = np.random.default_rng(2)
+    src = np.array([int(v) for v in rng.integers(16 + 6, 16 + 320 - 6, 3)]) - 16   # physical (x, y, z)
+    lo = np.clip(src - n // 2, 0, 320 - n)
+    vc = np.ascontiguousarray(vel[lo[2]:lo[2] + n + 1, lo[1]:lo[1] + n + 1, lo[0]:lo[0] + n + 1])
+    p = Pair(vc, npml, "fp32")
+    Nt = n + 2 * npml
+    s_loc = tuple(int(v) for v in src - lo + npml)
+    f = point_source((Nt, Nt, Nt), s_loc, H)
+    u, its, relres, rc = p.g.solve(p.dev(f), 1e-6)
+    assert rc == 0 and relres <= 1e-6
+    uo, its_o, rel_o, st = p.o.solve(f, 1e-10)
+    assert st == 0
+    u6, its6, rel6, st6 = p.o.solve(f, 1e-6)
+    err = rel(to_np(u), uo)
+    err6 = rel(u6, uo)
+    print(f"\nC2-crop FP32: |u_gpu - u_ref|/|u_ref| = {err:.3e} ({its} PC calls, relres {relres:.2e}); "
+          f"oracle at 1e-6: {err6:.3e} ({its6} calls); reference {its_o} calls to {rel_o:.1e}")
+    assert err <= 1e-5, (err, err6)
+
+
 # ---- adjoint gradient: transposes, row derivatives in m = 1/c^2, the gradient ----
 
 @pytest.mark.parametrize("level,op", [(0, 5), (0, 6), (0, 7), (1, 5), (1, 6), (2, 6)])
@@ -504,6 +585,28 @@ def test_grad_matches_oracle(precision):
     assert err <= (1e-7 if precision == "fp64" else 2e-3), err
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grad_with_checkpoint(precision):
+    """helm_grad with the forward solutions of helm_solve_checkpoint (no forward solve)
+    against the oracle's gradient, and the checkpointed u against helm_solve's."""
+    vel = grf_velocity(24, 20, 16, seed=42, corr_len=5.0)
+    p = Pair(vel, 4, precision)
+    nx, ny, nz = p.g.dims(0)
+    f = np.stack([point_source((nx, ny, nz), (11, 13, 10), H), point_source((nx, ny, nz), (19, 12, 14), H)])
+    s = np.stack([p.rand(0, 422), p.rand(0, 423)])
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    fd = p.dev(f)
+    u1, its1, rel1, rc1 = p.g.solve(fd, tol)
+    u2, v, its2, rel2, rc2 = p.g.solve_checkpoint(fd, tol)
+    assert rc1 == 0 and rc2 == 0 and list(its1) == list(its2) and torch.equal(u1, u2)
+    g, its, rels, rc = p.g.grad(fd, p.dev(s), tol, v=v)
+    assert rc == 0 and list(its[:, 0]) == [0, 0] and rels[:, 1].max() <= tol, (its, rels)
+    ref = sum(p.o.grad(f[r].astype(complex), s[r].astype(complex), 1e-11)[0] for r in range(2))
+    err = rel(g.cpu().numpy().astype(np.float64), ref)
+    print(f"\ncheckpointed gradient {precision}: {err:.3e}")
+    assert err <= (1e-7 if precision == "fp64" else 2e-3), err
+
+
 def test_c2_transpose_identity(c2):
     """At the full workload size: <A x, y> = <x, A^T y> (bilinear) for the FP32 GPU
     operators on every level, A and B (FP64 sums of the FP32 results)."""
@@ -539,7 +642,7 @@ def test_grad_edge_cases():
     fi = p.dev(f)
     its2 = np.zeros(2, np.int32)
     rel2 = np.zeros(2)
-    rc = helm.lib().helm_grad(p.g._h, ctypes.c_void_p(fi.data_ptr()), ctypes.c_void_p(fi.data_ptr()), 1, 1e-6,
+    rc = helm.lib().helm_grad(p.g._h, ctypes.c_void_p(fi.data_ptr()), ctypes.c_void_p(fi.data_ptr()), None, 1, 1e-6,
                               ctypes.c_void_p(gm.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb.value - 256,
                               its2.ctypes.data, rel2.ctypes.data)
     assert rc == -2
