@@ -16,8 +16,8 @@
  *                2^l h) has N_a / 2^l intervals and (N_a/2^l + 1) nodes.
  *   Layout       Grid functions are [z][y][x], x fastest, all nodes including
  *                the boundary, complex interleaved (re, im): complex128 in
- *                HELM_FP64 mode, complex64 in HELM_FP32 mode (the "precision
- *                vector type" below).  Nodes with an index 0 or N on any axis
+ *                HELM_FP64 mode, complex64 in HELM_FP32 and HELM_MIXED modes
+ *                (the "precision vector type" below).  Nodes with an index 0 or N on any axis
  *                are boundary nodes (u = 0, eq. helmholtz-pml): operators read
  *                them as zero and write zero there.
  *   Pointers     Grid functions, the velocity and the workspace are DEVICE
@@ -56,7 +56,18 @@ typedef enum {
     HELM_ENOTIMPL = -5
 } helm_status;
 
-typedef enum { HELM_FP64 = 0, HELM_FP32 = 1 } helm_precision;
+/* Arithmetic of the hot path (Sec. 5, arithmetic precision).  In every mode the
+ * outer FGMRES keeps its iterate, right-hand side and true residual in FP64 and
+ * sums every inner product in FP64.
+ *   HELM_FP64   complex128 vectors, FP64 arithmetic throughout.
+ *   HELM_FP32   complex64 vectors, FP32 stencil and vector arithmetic.
+ *   HELM_MIXED  as HELM_FP32, except that the vectors inside the 2h-4h cycle
+ *               (its Jacobi iterates and residual, the 4h basis, its Jacobi
+ *               images and correction) and K_2h's preconditioned vectors are
+ *               stored in IEEE half precision, scaled by the inverse norm of the
+ *               cycle's input and a fixed per-level factor (arithmetic stays
+ *               FP32).  Requires nJ_2h = nJ_4h = 2. */
+typedef enum { HELM_FP64 = 0, HELM_FP32 = 1, HELM_MIXED = 2 } helm_precision;
 
 /* Level operators accepted by helm_apply */
 typedef enum {
@@ -212,10 +223,14 @@ helm_status helm_residual_restrict(helm_hierarchy *H, int level, int op, const v
 helm_status helm_prolong_add(helm_hierarchy *H, int level, const void *coarse, void *fine);
 
 /* e = C_4h(q): m_4h CA-GMRES steps on B_4h from zero, right preconditioned by
- * J_nJ4h(B_4h; omega_4h) (Sec. 3.2).  q, e on level 2, zero boundary. */
+ * J_nJ4h(B_4h; omega_4h) (Sec. 3.2).  q, e on level 2, zero boundary.  In
+ * HELM_MIXED mode q is stored in half precision in units of its own norm, as
+ * inside the cycle, and e is returned in complex64. */
 helm_status helm_bottom(helm_hierarchy *H, const void *q, void *e);
 
-/* y = V^sigma_2h(q), one shifted 2h-4h cycle (eq. shifted-auxiliary-cycle). */
+/* y = V^sigma_2h(q), one shifted 2h-4h cycle (eq. shifted-auxiliary-cycle).
+ * In HELM_MIXED mode the cycle runs in units of the norm of q (a zero q gives
+ * a zero y) and y is returned in complex64. */
 helm_status helm_vcycle(helm_hierarchy *H, const void *q, void *y);
 
 /* e = K_2h(r): c_2h FGMRES(m_2h) cycles on A_2h from zero, right

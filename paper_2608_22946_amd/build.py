@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhelm.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["stencil.hip", "transfer.hip", "vector.hip", "adjoint.hip", "helm.hip", "noalloc.hip"]
+SOURCES = ["stencil.hip", "stencil_mixed.hip", "transfer.hip", "vector.hip", "adjoint.hip", "helm.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -15,6 +15,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "helm_internal.h"
@@ -67,6 +68,12 @@ struct helm_hierarchy {
     double *wd[3][3];
     float *atab_f, *btab_f, *ctab_f;
     double *atab_d, *btab_d;
+    // HELM_MIXED: FP16-stored vectors hold v * f * qs (helm_internal.h), f = fres[l] for
+    // residual-like vectors (the cycle input, residuals, the bottom basis P) and fsol[l]
+    // for correction-like ones (Jacobi iterates, corrections, Z); d_one is the qs of
+    // normalised cycle inputs
+    float fres[3], fsol[3];
+    double *d_one;
     int nlanes;
     Lane lane[kMaxLanes];
     std::string err;
@@ -136,6 +143,9 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     for (int l = 0; l < 3; ++l) level_geom(N, l, 1.0, g[l]);
     const size_t es = (o.precision == HELM_FP64) ? sizeof(c64) : sizeof(c32);
     auto vec = [&](int l) { return c.take<char>(es * (size_t)g[l].nn); };
+    // the preconditioner's inner vectors: FP16-stored in HELM_MIXED
+    const size_t es16 = (o.precision == HELM_MIXED) ? sizeof(c16) : es;
+    auto vec16 = [&](int l) { return c.take<char>(es16 * (size_t)g[l].nn); };
     helm_hierarchy dummy;
     helm_hierarchy *Hp = H ? H : &dummy;
     for (int l = 0; l < 3; ++l) {
@@ -150,6 +160,7 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     Hp->atab_f = c.take<float>(20 * (size_t)K);
     Hp->btab_f = c.take<float>(12 * (size_t)K);
     Hp->ctab_f = c.take<float>(24 * (size_t)(K + 1));
+    Hp->d_one = c.take<double>(1);
     Hp->atab_d = c.take<double>(20 * (size_t)K);
     Hp->btab_d = c.take<double>(12 * (size_t)K);
     const int nl = (o.lanes > 1) ? o.lanes : 1;
@@ -163,14 +174,14 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
         Ln.x64 = c.take<c64>(g[0].nn);
         Ln.b64 = c.take<c64>(g[0].nn);
         for (int j = 0; j <= o.m_2h; ++j) Ln.V2[j] = vec(1);
-        for (int j = 0; j < o.m_2h; ++j) Ln.Z2[j] = vec(1);
+        for (int j = 0; j < o.m_2h; ++j) Ln.Z2[j] = vec16(1);
         Ln.e2 = vec(1);
         Ln.r2 = vec(1);
-        Ln.vy = vec(1);
-        Ln.vr = vec(1);
-        for (int j = 0; j <= o.m_4h; ++j) Ln.P4[j] = vec(2);
-        for (int j = 0; j < o.m_4h; ++j) Ln.Z4[j] = vec(2);
-        Ln.e4 = vec(2);
+        Ln.vy = vec16(1);
+        Ln.vr = vec16(1);
+        for (int j = 0; j <= o.m_4h; ++j) Ln.P4[j] = vec16(2);
+        for (int j = 0; j < o.m_4h; ++j) Ln.Z4[j] = vec16(2);
+        Ln.e4 = vec16(2);
         for (int l = 0; l < 3; ++l) Ln.tmp[l] = vec(l);
         for (int l = 0; l < 2; ++l)
             Ln.wrest[l] = c.take<char>(es * (size_t)(g[l].n[2] / 2 + 1) * (g[l].n[1] + 1) * (g[l].n[0] / 2 + 1));
@@ -458,8 +469,122 @@ struct Eng {
 
     // K_2h(r), eq. unshifted-middle-solve
     hipError_t k2h(const T *r, T *e) {
+        if constexpr (std::is_same<T, c32>::value)
+            if (H->prec == HELM_MIXED) return k2h_mixed(r, e);
         auto prec = [this](const T *in, T *out) { return vcycle(in, out); };
         return gmres(1, false, prec, r, e, true, H->opt.m_2h, H->opt.c_2h, Ln->st_k2h, Ln->V2, Ln->Z2);
+    }
+
+    // ---- HELM_MIXED (FP32 arithmetic, FP16-stored inner vectors; Sec. 5 "Arithmetic Precision") ----
+    // The V-cycle's iterates y and r, the 4h basis P, Z and correction e, and K_2h's
+    // preconditioned vectors Z are stored as c16 with the scales of helm_hierarchy::fres /
+    // fsol times qs, the inverse norm of the cycle's input (the K_2h state's vs0 for its
+    // unnormalised first basis vector, 1 for the others).  Every V-cycle map is homogeneous
+    // of degree one in its input, so these units keep the stored values near unit size.
+    Scale sres(int l, const double *qs) const { return {H->fres[l], qs}; }
+    Scale ssol(int l, const double *qs) const { return {H->fsol[l], qs}; }
+    static c16 *h16(void *p) { return static_cast<c16 *>(p); }
+
+    template <typename TX, typename TG, typename TY>
+    hipError_t st16(int l, int mode, bool shifted, double wJ, const void *x, const void *g, const void *base, void *y,
+                    Scale sx, Scale sg, Scale sb, Scale sy) {
+        StencilCall c{mode, shifted ? 1 : 0, wJ, x, g, base, y, false, EPI_NORM_INIT, nullptr, 0};
+        c.sx = sx;
+        c.sg = sg;
+        c.sb = sb;
+        c.sy = sy;
+        return launch_stencil<R, TX, TG, TY>(L(l), c, Ln->rb, s);
+    }
+
+    // C_4h on FP16-stored vectors: basis P (residual units), Z = J(P) and e (correction units);
+    // the Gram solve and the combination are invariant to the common scales
+    hipError_t bottom_mixed(const c16 *q, const double *qs, c16 *e) {
+        const int m = H->opt.m_4h;
+        c16 *P[kM4Max + 1], *Zb[kM4Max];
+        P[0] = const_cast<c16 *>(q);
+        for (int j = 1; j <= m; ++j) P[j] = h16(Ln->P4[j]);
+        for (int j = 0; j < m; ++j) Zb[j] = h16(Ln->Z4[j]);
+        const Scale sr = sres(2, qs), ss = ssol(2, qs);
+        for (int j = 0; j < m; ++j) {
+            HIP_CHK((st16<c16, c16, c16>(2, M_JAC2, true, H->opt.omega_4h, nullptr, P[j], nullptr, Zb[j], sr, sr, ss,
+                                         ss)));
+            HIP_CHK((st16<c16, c16, c16>(2, M_APPLY, true, 0.0, Zb[j], nullptr, nullptr, P[j + 1], ss, sr, ss, sr)));
+        }
+        HIP_CHK(launch_gram<c16>((const c16 *const *)P, m + 1, nn(2), Ln->st_bottom, Ln->rb, s));
+        return launch_combine<c16, c16>(e, (const c16 *const *)Zb, m, nn(2), Ln->st_bottom, false, true, s);
+    }
+
+    // V^sigma_2h(q) with FP16-stored iterates; q in FP32 (true values), out = Z in correction units
+    hipError_t vcycle_mixed(const T *q, const double *qs, c16 *out) {
+        const helm_options &o = H->opt;
+        c16 *y = h16(Ln->vy), *r = h16(Ln->vr), *q4 = h16(Ln->P4[0]), *e4 = h16(Ln->e4);
+        const Scale one = {1.0f, nullptr}, s1 = ssol(1, qs), r1 = sres(1, qs), r2 = sres(2, qs), s2 = ssol(2, qs);
+        HIP_CHK((st16<c32, c32, c16>(1, M_JAC2, true, o.omega_2h, nullptr, q, nullptr, y, one, one, one, s1)));   // y = J(B, q)
+        HIP_CHK((st16<c16, c32, c32>(1, M_RESID_R, true, 0.0, y, q, nullptr, Ln->wrest[1], s1, one, one, one)));
+        HIP_CHK((launch_restrict_y<c32, c16>(H->geom[1], H->geom[2], static_cast<const c32 *>(Ln->wrest[1]), q4, s,
+                                             r2)));                                                   // q4 = R(q - B y)
+        HIP_CHK(bottom_mixed(q4, qs, e4));                                                             // e4 = C_4h(q4)
+        HIP_CHK((launch_prolong_add<c16, c16>(H->geom[2], H->geom[1], e4, y, s, s2, s1)));            // y~ = y + P e4
+        HIP_CHK((st16<c16, c32, c16>(1, M_RESID, true, 0.0, y, q, nullptr, r, s1, one, one, r1)));    // r = q - B y~
+        return st16<c16, c16, c16>(1, M_JAC2_ADD, true, o.omega_2h, nullptr, r, y, out, r1, r1, s1, s1);   // y~ + J(B, r)
+    }
+
+    // helm_vcycle / helm_bottom on caller vectors: in HELM_MIXED the input's own inverse
+    // norm gives the FP16 units, and the result is returned in FP32
+    hipError_t vcycle_hook(const T *q, T *y) {
+        if constexpr (std::is_same<T, c32>::value)
+            if (H->prec == HELM_MIXED) {
+                KState *st = Ln->st_hook;
+                c16 *z = h16(Ln->Z2[0]);
+                HIP_CHK(launch_dots<T>(nullptr, 0, q, true, nn(1), EPI_NORM_INIT, st, 0, nullptr, Ln->rb, s));
+                HIP_CHK(vcycle_mixed(q, &st->vs0, z));
+                return launch_convert_scaled<c16, c32>(z, y, nn(1), ssol(1, &st->vs0), Scale{1.0f, nullptr}, s);
+            }
+        return vcycle(q, y);
+    }
+    hipError_t bottom_hook(const T *q, T *e) {
+        if constexpr (std::is_same<T, c32>::value)
+            if (H->prec == HELM_MIXED) {
+                KState *st = Ln->st_hook;
+                c16 *q4 = h16(Ln->P4[0]), *e4 = h16(Ln->e4);
+                const Scale one = {1.0f, nullptr};
+                HIP_CHK(launch_dots<T>(nullptr, 0, q, true, nn(2), EPI_NORM_INIT, st, 0, nullptr, Ln->rb, s));
+                HIP_CHK((launch_convert_scaled<c32, c16>(q, q4, nn(2), one, sres(2, &st->vs0), s)));
+                HIP_CHK(bottom_mixed(q4, &st->vs0, e4));
+                return launch_convert_scaled<c16, c32>(e4, e, nn(2), ssol(2, &st->vs0), one, s);
+            }
+        return bottom(q, e);
+    }
+
+    // K_2h with FP16-stored Z: FGMRES on A_2h (FP32 basis, FP64 sums), V-cycle on each basis vector
+    hipError_t k2h_mixed(const T *r, T *e) {
+        const int m = H->opt.m_2h;
+        KState *st = Ln->st_k2h;
+        T *V[kMMax + 1];
+        c16 *Zp[kMMax];
+        for (int j = 0; j <= m; ++j) V[j] = v(Ln->V2[j]);
+        for (int j = 0; j < m; ++j) Zp[j] = h16(Ln->Z2[j]);
+        const Scale one = {1.0f, nullptr};
+        for (int cyc = 0; cyc < H->opt.c_2h; ++cyc) {
+            const bool from_zero = (cyc == 0);
+            if (from_zero) {
+                V[0] = const_cast<T *>(r);   // read only
+                HIP_CHK(launch_dots<T>(nullptr, 0, r, true, nn(1), EPI_NORM_INIT, st, 0, nullptr, Ln->rb, s));
+            } else {
+                V[0] = v(Ln->V2[0]);
+                HIP_CHK(stencil(1, M_RESID, false, 0.0, e, r, nullptr, V[0], true, st));
+            }
+            for (int k = 0; k < m; ++k) {
+                const double *qs = (k == 0) ? &st->vs0 : H->d_one;   // V_0 is kept unnormalised
+                HIP_CHK(vcycle_mixed(V[k], qs, Zp[k]));
+                HIP_CHK((st16<c16, c16, c32>(1, M_APPLY, false, 0.0, Zp[k], nullptr, nullptr, V[k + 1], ssol(1, qs), one,
+                                             one, one)));
+                HIP_CHK(arnoldi(1, V, k, st, k == m - 1));
+            }
+            HIP_CHK((launch_combine<c32, c16>(e, (const c16 *const *)Zp, m, nn(1), st, true, from_zero, s,
+                                             H->fsol[1])));
+        }
+        return hipSuccess;
     }
 
     // S_h(g; x0) -> x (in place when x0 == x): one GMRES(m_h) cycle right-preconditioned by J_nJh(A_h).
@@ -624,7 +749,14 @@ void release_lanes(helm_hierarchy *H) {
 helm_status check_options(const helm_options *o, std::string &msg) {
     if (!o) { msg = "options pointer is NULL"; return HELM_EINVAL; }
     if (o->struct_size != (int)sizeof(helm_options)) { msg = "options.struct_size mismatch"; return HELM_EINVAL; }
-    if (o->precision != HELM_FP64 && o->precision != HELM_FP32) { msg = "unknown precision"; return HELM_EINVAL; }
+    if (o->precision != HELM_FP64 && o->precision != HELM_FP32 && o->precision != HELM_MIXED) {
+        msg = "unknown precision";
+        return HELM_EINVAL;
+    }
+    if (o->precision == HELM_MIXED && (o->nJ_2h != 2 || o->nJ_4h != 2)) {
+        msg = "HELM_MIXED runs the fused two-sweep Jacobi on the 2h and 4h levels: nJ_2h and nJ_4h must be 2";
+        return HELM_EINVAL;
+    }
     if (!(o->sigma >= 0) || !(o->omega_h > 0) || !(o->omega_2h > 0) || !(o->omega_4h > 0) || !(o->gamma_max >= 0) ||
         !std::isfinite(o->sigma) || !std::isfinite(o->gamma_max)) {
         msg = "sigma, Jacobi weights and gamma_max must be finite (weights > 0)";
@@ -679,8 +811,9 @@ bool level_ok(int l) { return l >= 0 && l <= 2; }
 template <typename T>
 hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     Eng<T> E(H);
+    // working-precision vectors large enough for the level (the V-cycle ones are FP16 in HELM_MIXED)
     T *x = static_cast<T *>(H->lane[0].tmp[l]);
-    T *y = static_cast<T *>(l == 0 ? H->lane[0].Vs[0] : (l == 1 ? H->lane[0].vy : H->lane[0].e4));
+    T *y = static_cast<T *>(l == 0 ? H->lane[0].Vs[0] : (l == 1 ? H->lane[0].V2[1] : H->lane[0].Vs[1]));
     HIP_CHK(launch_fill_zero<T>(x, E.nn(l), H->s));
     hipEvent_t a, b;
     HIP_CHK(hipEventCreate(&a));
@@ -940,6 +1073,17 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
         (e = hipMemcpyAsync(H->btab_f, btf.data(), btf.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return bail(HELM_EHIP, std::string("table upload: ") + hipGetErrorString(e));
+    for (int l = 0; l < 3; ++l) {
+        // FP16 units: a cycle input of unit norm has entries of RMS 1/64; D^-1 ~ ell^2 / 4
+        H->fres[l] = (float)(std::sqrt((double)H->geom[l].nn) / 64.0);
+        H->fsol[l] = (float)(H->fres[l] * 4.0 / (H->geom[l].ell * H->geom[l].ell));
+    }
+    {
+        static const double one = 1.0;
+        if ((e = hipMemcpyAsync(H->d_one, &one, sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return bail(HELM_EHIP, std::string("upload: ") + hipGetErrorString(e));
+    }
     for (int l = 0; l < 3; ++l) {
         fill_level_args<float>(H, l, H->Lf[l], H->wf[l][0], H->wf[l][1], H->wf[l][2], H->atab_f, H->btab_f);
         fill_level_args<double>(H, l, H->Ld[l], H->wd[l][0], H->wd[l][1], H->wd[l][2], H->atab_d, H->btab_d);
@@ -1227,7 +1371,7 @@ helm_status helm_bottom(helm_hierarchy *H, const void *q, void *e) {
     if (!q || !e || q == e) return fail(H, HELM_EINVAL, "invalid bottom arguments");
     return dispatch(H, [&](auto E) {
         using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
-        return E.bottom((const TT *)q, (TT *)e);
+        return E.bottom_hook((const TT *)q, (TT *)e);
     });
 }
 
@@ -1236,7 +1380,7 @@ helm_status helm_vcycle(helm_hierarchy *H, const void *q, void *y) {
     if (!q || !y || q == y) return fail(H, HELM_EINVAL, "invalid vcycle arguments");
     return dispatch(H, [&](auto E) {
         using TT = typename std::remove_reference<decltype(*E.v(nullptr))>::type;
-        return E.vcycle((const TT *)q, (TT *)y);
+        return E.vcycle_hook((const TT *)q, (TT *)y);
     });
 }
 

@@ -42,6 +42,51 @@ struct cplx {
 };
 using c32 = cplx<float>;
 using c64 = cplx<double>;
+// FP16-stored complex (HELM_MIXED): the preconditioner's inner vectors in 4 B per node.
+// A stored vector holds v * f * (*qs) for its true value v: f a level constant, *qs the
+// inverse norm of the cycle's input (device memory), so stored values stay near unit size
+// whatever the grid spacing and the source strength.
+using c16 = cplx<_Float16>;
+struct Scale {
+    float f;             // constant factor
+    const double *qs;    // device scalar; null for vectors stored in FP32 / FP64
+};
+constexpr float kHalfMax = 65504.0f;   // largest finite FP16 value
+
+template <typename T>
+constexpr bool is_half() { return sizeof(T{}.re) == 2; }
+template <typename R>
+__device__ __forceinline__ R sat_half(R a) {   // keeps NaN, clamps to the finite FP16 range
+    return a > (R)kHalfMax ? (R)kHalfMax : (a < -(R)kHalfMax ? -(R)kHalfMax : a);
+}
+// element of type T from a true value (c16: times the store multiplier s, saturated)
+template <typename T, typename R>
+__device__ __forceinline__ T to_stored(R re, R im, R s) {
+    T o;
+    if constexpr (is_half<T>()) {
+        o.re = (_Float16)sat_half(re * s);
+        o.im = (_Float16)sat_half(im * s);
+    } else {
+        o.re = re;
+        o.im = im;
+    }
+    return o;
+}
+// multipliers of a kernel's operands: 1 / (f qs) after a c16 load, f qs before a c16 store, else 1.
+// qs = 0 (the inverse norm of a zero input) stores zeros, which load as zeros.
+template <typename R, typename T>
+__device__ __forceinline__ R load_mul(const Scale &s) {
+    if constexpr (is_half<T>()) {
+        const double d = (double)s.f * *s.qs;
+        return d != 0.0 ? (R)(1.0 / d) : (R)0;
+    }
+    return (R)1;
+}
+template <typename R, typename T>
+__device__ __forceinline__ R store_mul(const Scale &s) {
+    if constexpr (is_half<T>()) return (R)((double)s.f * *s.qs);
+    return (R)1;
+}
 
 // ---------------------------------------------------------------------------
 // Geometry and per-level kernel arguments
@@ -139,6 +184,7 @@ struct StencilCall {
     int epi;
     KState *st;
     int k;
+    Scale sx = {1.0f, nullptr}, sg = {1.0f, nullptr}, sb = {1.0f, nullptr}, sy = {1.0f, nullptr};   // c16 operands
 };
 
 // R = arithmetic type, TX/TG/TY = element types of x, g, y (c32 or c64)
@@ -156,10 +202,12 @@ hipError_t launch_restrict(const Geom &fine, const Geom &coarse, const T *f, T *
 
 // second pass of the fused residual + full weighting: coarse = y-weights of the
 // x/z-restricted residual rows w ([coarse z][fine y][coarse x]); zero on the coarse boundary
-template <typename T>
-hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, T *c, hipStream_t s);
-template <typename T>
-hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, T *f, hipStream_t s);
+template <typename T, typename TO = T>
+hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, TO *c, hipStream_t s,
+                             Scale so = {1.0f, nullptr});
+template <typename T, typename TF = T>
+hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, TF *f, hipStream_t s,
+                              Scale sc = {1.0f, nullptr}, Scale sf = {1.0f, nullptr});
 
 template <typename T>
 hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long long n, int epi, KState *st, int k,
@@ -174,10 +222,16 @@ hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KStat
 
 
 // x (+)= sum_j y_j Z_j with y from the state: back substitution of the
-// rotated Hessenberg (from_backsolve) or the stored s-step coefficients.
+// rotated Hessenberg (from_backsolve) or the stored s-step coefficients.  With
+// c16 Z and a c32 / c64 x, Z_j is stored with the scale zf * qs_j, qs_0 = st->vs0
+// (the cycle's first basis vector kept unnormalised) and qs_j = 1 for j >= 1;
+// with c16 Z and c16 x both carry the same scale (no conversion).
 template <typename TX, typename TZ>
 hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, KState *st, bool from_backsolve,
-                          bool overwrite, hipStream_t s);
+                          bool overwrite, hipStream_t s, float zf = 1.0f);
+// y = x with the scales of c16 operands applied (true values in, true values out)
+template <typename TI, typename TO>
+hipError_t launch_convert_scaled(const TI *x, TO *y, long long n, Scale si, Scale so, hipStream_t s);
 
 template <typename T>
 hipError_t launch_gram(const T *const *P, int np, long long n, KState *st, const RedBuf &rb, hipStream_t s);

@@ -4,6 +4,7 @@
 // Coarse interior nodes only touch fine interior nodes, boundary values read as
 // zero, boundary outputs are zero (restriction) or left unchanged (prolong-add).
 #include <algorithm>
+#include <type_traits>
 
 #include "helm_internal.h"
 
@@ -48,10 +49,12 @@ __global__ void __launch_bounds__(256) k_restrict(Geom F, Geom C, const T *__res
 // residual already weighted along x and z; coarse node (X, Y, Z) takes the
 // fine rows 2Y-1, 2Y, 2Y+1 with weights 1/4, 1/2, 1/4.  Coarse boundary nodes
 // are written as zero.
-template <typename T>
-__global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__restrict__ w, T *__restrict__ c) {
+template <typename T, typename TO>
+__global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__restrict__ w, TO *__restrict__ c,
+                                                   Scale so) {
     const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zc = blockIdx.z;
     if (X > C.n[0] || Y > C.n[1]) return;
+    const real_of<T> ms = store_mul<real_of<T>, TO>(so);
     real_of<T> sr = 0, si = 0;
     if (X >= 1 && X <= C.n[0] - 1 && Y >= 1 && Y <= C.n[1] - 1 && Zc >= 1 && Zc <= C.n[2] - 1) {
         const long long wsx = C.n[0] + 1, wsy = (long long)(F.n[1] + 1) * wsx;
@@ -60,10 +63,7 @@ __global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__r
         sr = (real_of<T>)0.25 * (a.re + d.re) + (real_of<T>)0.5 * b.re;
         si = (real_of<T>)0.25 * (a.im + d.im) + (real_of<T>)0.5 * b.im;
     }
-    T o;
-    o.re = sr;
-    o.im = si;
-    c[(long long)Zc * C.sy + (long long)Y * C.sx + X] = o;
+    c[(long long)Zc * C.sy + (long long)Y * C.sx + X] = to_stored<TO>(sr, si, ms);
 }
 
 // fine += P coarse, one thread per coarse cell (X, Y, Z), X in [0, nc): it
@@ -74,11 +74,14 @@ __global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__r
 // fine boundary nodes are left unchanged.  Each coarse value is loaded once per
 // cell instead of once per fine node, and the two x-neighbouring fine nodes of
 // a cell are adjacent in memory.
-template <typename T>
-__global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__restrict__ c, T *__restrict__ f) {
-    using R = real_of<T>;
+template <typename T, typename TF>
+__global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__restrict__ c, TF *__restrict__ f,
+                                                    Scale sc, Scale sf) {
+    using R = std::conditional_t<is_half<TF>(), float, real_of<TF>>;   // FP16-stored vectors add in FP32
     const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Z = blockIdx.z;
     if (X >= C.n[0] || Y >= C.n[1]) return;
+    // c16 operands: coarse values to true units, fine values through the fine scale
+    const R mc = load_mul<R, T>(sc), mfl = load_mul<R, TF>(sf), mfs = store_mul<R, TF>(sf);
     // coarse corner values, zero outside the coarse interior
     R cr[2][2][2], ci[2][2][2];
 #pragma unroll
@@ -94,8 +97,8 @@ __global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__
                 v.re = 0;
                 v.im = 0;
                 if (in) v = c[(long long)Zc * C.sy + (long long)Yc * C.sx + Xc];
-                cr[cz][cy][cx] = v.re;
-                ci[cz][cy][cx] = v.im;
+                cr[cz][cy][cx] = (R)v.re * mc;
+                ci[cz][cy][cx] = (R)v.im * mc;
             }
     const R half = (R)0.5;
 #pragma unroll
@@ -119,17 +122,13 @@ __global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__
                 pr[cx] = j ? half * (zr[0] + zr[1]) : zr[0];
                 pi[cx] = j ? half * (zi[0] + zi[1]) : zi[0];
             }
-            T *row = f + (long long)z * F.sy + (long long)y * F.sx + 2 * X;
+            TF *row = f + (long long)z * F.sy + (long long)y * F.sx + 2 * X;
             if (X >= 1) {   // fine node 2X (x = 0 is a boundary node)
-                T o = row[0];
-                o.re += pr[0];
-                o.im += pi[0];
-                row[0] = o;
+                const TF o = row[0];
+                row[0] = to_stored<TF, R>((R)o.re * mfl + pr[0], (R)o.im * mfl + pi[0], mfs);
             }
-            T o = row[1];   // fine node 2X + 1
-            o.re += half * (pr[0] + pr[1]);
-            o.im += half * (pi[0] + pi[1]);
-            row[1] = o;
+            const TF o = row[1];   // fine node 2X + 1
+            row[1] = to_stored<TF, R>((R)o.re * mfl + half * (pr[0] + pr[1]), (R)o.im * mfl + half * (pi[0] + pi[1]), mfs);
         }
     }
 }
@@ -152,25 +151,33 @@ hipError_t launch_restrict(const Geom &fine, const Geom &coarse, const T *f, T *
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, T *c, hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict_y<T>), node_grid(coarse), dim3(kTX, kTY), 0, s, fine, coarse, w, c);
+template <typename T, typename TO>
+hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, TO *c, hipStream_t s, Scale so) {
+    if (is_half<TO>() && !so.qs) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_restrict_y<T, TO>), node_grid(coarse), dim3(kTX, kTY), 0, s, fine, coarse, w, c, so);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, T *f, hipStream_t s) {
+template <typename T, typename TF>
+hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, TF *f, hipStream_t s, Scale sc,
+                              Scale sf) {
     if (fine.n[0] != 2 * coarse.n[0] || fine.n[1] != 2 * coarse.n[1] || fine.n[2] != 2 * coarse.n[2])
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_prolong_add<T>), cell_grid(coarse), dim3(kTX, kTY), 0, s, coarse, fine, c, f);
+    if ((is_half<T>() && !sc.qs) || (is_half<TF>() && !sf.qs)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_prolong_add<T, TF>), cell_grid(coarse), dim3(kTX, kTY), 0, s, coarse, fine, c, f, sc, sf);
     return hipGetLastError();
 }
 
 template hipError_t launch_restrict<c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t);
 template hipError_t launch_restrict<c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t);
-template hipError_t launch_restrict_y<c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t);
-template hipError_t launch_restrict_y<c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t);
-template hipError_t launch_prolong_add<c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t);
-template hipError_t launch_prolong_add<c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t);
+template hipError_t launch_restrict_y<c32, c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t, Scale);
+template hipError_t launch_restrict_y<c64, c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t, Scale);
+template hipError_t launch_restrict_y<c32, c16>(const Geom &, const Geom &, const c32 *, c16 *, hipStream_t, Scale);
+template hipError_t launch_prolong_add<c32, c32>(const Geom &, const Geom &, const c32 *, c32 *, hipStream_t, Scale,
+                                                 Scale);
+template hipError_t launch_prolong_add<c64, c64>(const Geom &, const Geom &, const c64 *, c64 *, hipStream_t, Scale,
+                                                 Scale);
+template hipError_t launch_prolong_add<c16, c16>(const Geom &, const Geom &, const c16 *, c16 *, hipStream_t, Scale,
+                                                 Scale);
 
 }  // namespace helm

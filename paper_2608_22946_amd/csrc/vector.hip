@@ -7,6 +7,7 @@
 // small dense epilogue (Givens rotation, back substitution, Cholesky) in FP64,
 // so that no host synchronisation is needed inside a preconditioner call.
 #include <algorithm>
+#include <type_traits>
 
 #include "helm_internal.h"
 
@@ -42,6 +43,13 @@ __device__ __forceinline__ c32 ldnt(const c32 *p) {
     c32 o;
     o.re = __int_as_float((int)v);
     o.im = __int_as_float((int)(v >> 32));
+    return o;
+}
+__device__ __forceinline__ c16 ldnt(const c16 *p) {
+    const unsigned v = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(p));
+    c16 o;
+    o.re = __builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
+    o.im = __builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
     return o;
 }
 __device__ __forceinline__ c64 ldnt(const c64 *p) {
@@ -370,36 +378,53 @@ __global__ void __launch_bounds__(64) k_backsolve(KState *st, int nv) {
 // s-step Gram solve)
 template <typename TX, typename TZ, int NV>
 __global__ void __launch_bounds__(256) k_combine(TX *__restrict__ x, Ptrs<TZ, NV> Zp, long long n, const KState *st,
-                                                int overwrite) {
+                                                int overwrite, float zf) {
+    using RA = std::conditional_t<is_half<TX>(), float, real_of<TX>>;   // FP16-stored x adds in FP32
     __shared__ double ys[NV][2];
     if (threadIdx.x < NV) {
-        ys[threadIdx.x][0] = st->y[threadIdx.x][0];
-        ys[threadIdx.x][1] = st->y[threadIdx.x][1];
+        // c16 Z into a c32 / c64 x: the coefficient takes Z_j's inverse scale 1 / (zf qs_j)
+        double w = 1.0;
+        if (is_half<TZ>() && !is_half<TX>()) {
+            const double d = (double)zf * (threadIdx.x == 0 ? st->vs0 : 1.0);
+            w = d != 0.0 ? 1.0 / d : 0.0;
+        }
+        ys[threadIdx.x][0] = st->y[threadIdx.x][0] * w;
+        ys[threadIdx.x][1] = st->y[threadIdx.x][1] * w;
     }
     __syncthreads();
-    real_of<TX> yr[NV], yi[NV];
+    RA yr[NV], yi[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        yr[j] = (real_of<TX>)ys[j][0];
-        yi[j] = (real_of<TX>)ys[j][1];
+        yr[j] = (RA)ys[j][0];
+        yi[j] = (RA)ys[j][1];
     }
     const long long i = elem_index();
     if (i >= n) return;
-    TX acc;
-    if (overwrite) {
-        acc.re = 0;
-        acc.im = 0;
-    } else {
-        acc = x[i];
+    RA ar = 0, ai = 0;
+    if (!overwrite) {
+        const TX v = x[i];
+        ar = (RA)v.re;
+        ai = (RA)v.im;
     }
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         const TZ z = ldnt(Zp.v[j] + i);
-        const real_of<TX> zr = (real_of<TX>)z.re, zi = (real_of<TX>)z.im;
-        acc.re += yr[j] * zr - yi[j] * zi;
-        acc.im += yr[j] * zi + yi[j] * zr;
+        const RA zr = (RA)z.re, zi = (RA)z.im;
+        ar += yr[j] * zr - yi[j] * zi;
+        ai += yr[j] * zi + yi[j] * zr;
     }
-    x[i] = acc;
+    x[i] = to_stored<TX, RA>(ar, ai, (RA)1);
+}
+
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_convert_scaled(const TI *__restrict__ x, TO *__restrict__ y, long long n,
+                                                       Scale si, Scale so) {
+    using RA = std::conditional_t<is_half<TO>(), float, real_of<TO>>;
+    const long long i = elem_index();
+    if (i >= n) return;
+    const RA mi = load_mul<RA, TI>(si), mo = store_mul<RA, TO>(so);
+    const TI v = x[i];
+    y[i] = to_stored<TO, RA>((RA)v.re * mi, (RA)v.im * mi, mo);
 }
 
 // Gram matrix G_ij = <P_i, P_j> (i <= j) of the s-step basis P_0..P_{NP-1}, then
@@ -698,7 +723,7 @@ hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KStat
 
 template <typename TX, typename TZ>
 hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, KState *st, bool from_backsolve,
-                          bool overwrite, hipStream_t s) {
+                          bool overwrite, hipStream_t s, float zf) {
     if (nz < 1 || nz > kMMax) return hipErrorInvalidValue;
     if (from_backsolve) {
         hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, st, nz);
@@ -709,7 +734,7 @@ hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, KState
 #define HELM_CB(NV)                                                                                            \
     case NV:                                                                                                   \
         hipLaunchKernelGGL((k_combine<TX, TZ, NV>), dim3(nb), dim3(256), 0, s, x, pack<TZ, NV>(Z), n, st,       \
-                           (int)overwrite);                                                                    \
+                           (int)overwrite, zf);                                                                \
         break;
     switch (nz) {
         HELM_CB(1) HELM_CB(2) HELM_CB(3) HELM_CB(4) HELM_CB(5) HELM_CB(6) HELM_CB(7) HELM_CB(8) HELM_CB(9)
@@ -783,11 +808,25 @@ HELM_INST(c32)
 HELM_INST(c64)
 #undef HELM_INST
 template hipError_t launch_combine<c32, c32>(c32 *, const c32 *const *, int, long long, KState *, bool, bool,
-                                             hipStream_t);
+                                             hipStream_t, float);
 template hipError_t launch_combine<c64, c64>(c64 *, const c64 *const *, int, long long, KState *, bool, bool,
-                                             hipStream_t);
+                                             hipStream_t, float);
 template hipError_t launch_combine<c64, c32>(c64 *, const c32 *const *, int, long long, KState *, bool, bool,
-                                             hipStream_t);
+                                             hipStream_t, float);
+template hipError_t launch_combine<c32, c16>(c32 *, const c16 *const *, int, long long, KState *, bool, bool,
+                                             hipStream_t, float);
+template hipError_t launch_combine<c16, c16>(c16 *, const c16 *const *, int, long long, KState *, bool, bool,
+                                             hipStream_t, float);
+template hipError_t launch_gram<c16>(const c16 *const *, int, long long, KState *, const RedBuf &, hipStream_t);
+
+template <typename TI, typename TO>
+hipError_t launch_convert_scaled(const TI *x, TO *y, long long n, Scale si, Scale so, hipStream_t s) {
+    if ((is_half<TI>() && !si.qs) || (is_half<TO>() && !so.qs)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_convert_scaled<TI, TO>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n, si, so);
+    return hipGetLastError();
+}
+template hipError_t launch_convert_scaled<c32, c16>(const c32 *, c16 *, long long, Scale, Scale, hipStream_t);
+template hipError_t launch_convert_scaled<c16, c32>(const c16 *, c32 *, long long, Scale, Scale, hipStream_t);
 template hipError_t launch_convert<c32, c64>(const c32 *, c64 *, long long, hipStream_t);
 template hipError_t launch_convert<c64, c32>(const c64 *, c32 *, long long, hipStream_t);
 template hipError_t launch_convert<c32, c32>(const c32 *, c32 *, long long, hipStream_t);

@@ -3,7 +3,7 @@
 Every step of the computation runs in libhelm.so on the GPU; PyTorch provides
 device memory (torch tensors) and the stream.  Grid functions are torch
 complex tensors of shape (Nz+1, Ny+1, Nx+1) on the level's total grid:
-complex64 for precision "fp32", complex128 for "fp64".
+complex64 for precision "fp32" and "mixed", complex128 for "fp64".
 """
 import ctypes
 import json
@@ -19,7 +19,8 @@ _DEFAULT_TABLE = os.path.join(os.path.dirname(_HERE), "workloads", "iofd_table.j
 HELM_OK, HELM_NOT_CONVERGED = 0, 1
 OP_A, OP_B, OP_Q, OP_DIAG_A, OP_DIAG_B = 0, 1, 2, 3, 4
 OP_AT, OP_BT, OP_QT, OP_DA, OP_DQ = 5, 6, 7, 8, 9   # transposes and row derivatives in m = 1/c^2
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
+_PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
 
 _c_int, _c_double, _c_void_p, _c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -128,7 +129,9 @@ class Hierarchy:
         vel = torch.as_tensor(velocity, dtype=torch.float32).to(self.device).contiguous()
         nz, ny, nx = (s - 1 for s in vel.shape)
         o = default_options()
-        o.precision = FP64 if precision == "fp64" else FP32
+        if precision not in _PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
+        o.precision = _PRECISIONS[precision]
         for k, v in params.items():
             if not hasattr(o, k):
                 raise TypeError(f"unknown option {k}")

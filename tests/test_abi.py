@@ -77,6 +77,23 @@ def test_bad_dims_rejected(L, dims, n_pml):
     assert L.helm_last_error(None)
 
 
+def test_mixed_workspace_is_smaller_and_needs_two_sweeps(L):
+    """HELM_MIXED keeps the 2h-4h cycle's vectors and K_2h's Z in half precision
+    (4 bytes per complex node) and runs only the fused two-sweep Jacobi there."""
+    rc, b32 = _ws(L, (56, 56, 56), 4, _opts(precision=helm.FP32))
+    rc2, bmx = _ws(L, (56, 56, 56), 4, _opts(precision=helm.MIXED))
+    assert rc == 0 and rc2 == 0
+    n1, n2 = 33 ** 3, 17 ** 3
+    # Z2 (10) + y, r at 2h and P (5) + Z (4) + e at 4h drop from 8 to 4 bytes per node
+    saved = 4 * (12 * n1 + 10 * n2)
+    assert abs((b32 - bmx) - saved) <= 256 * 40, (b32 - bmx, saved)
+    for field in ("nJ_2h", "nJ_4h"):
+        for nj in (1, 3):
+            rc, _ = _ws(L, (56, 56, 56), 4, _opts(precision=helm.MIXED, **{field: nj}))
+            assert rc == -1
+            assert b"nJ_2h and nJ_4h must be 2" in L.helm_last_error(None)
+
+
 def test_workspace_grows_by_one_solver_copy_per_lane(L):
     sizes = [_ws(L, (56, 56, 56), 4, _opts(lanes=k))[1] for k in (1, 2, 3)]
     assert sizes[1] > sizes[0] and sizes[2] - sizes[1] == sizes[1] - sizes[0]

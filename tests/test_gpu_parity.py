@@ -515,21 +515,22 @@ def test_c2_solve_residual(c2):
     assert true_rel <= 1.2e-6, (true_rel, relres, its)
 
 
-def test_c2_crop_solution_fp32(c2):
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_c2_crop_solution(c2, precision):
     """Converged-solution parity on the benchmark's own physics: a 64^3-cell crop of
     the 320^3 GRF velocity (seed 2, correlation length 20 cells, 2000 m/s +-25%
     clipped to [1500, 3000]) around the benchmark's seeded source, plus 16 PML cells
     (96^3 total), 6 points per wavelength at the crop's minimum velocity, the
-    derived table (Q_h included).  FP32 GPU solve to 1e-6 against the FP64 oracle
-    solved to 1e-10, every node; the oracle stopped at 1e-6 is measured beside it
-    (the error a 1e-6 residual allows in FP64 arithmetic)."""
+    derived table (Q_h included).  FP32 (or HELM_MIXED) GPU solve to 1e-6 against
+    the FP64 oracle solved to 1e-10, every node; the oracle stopped at 1e-6 is
+    measured beside it (the error a 1e-6 residual allows in FP64 arithmetic)."""
     _, vel = c2
     n, npml, N = 64, 16, 352
     rng = np.random.default_rng(2)
     src = np.array([int(v) for v in rng.integers(16 + 6, 16 + 320 - 6, 3)]) - 16   # physical (x, y, z)
     lo = np.clip(src - n // 2, 0, 320 - n)
     vc = np.ascontiguousarray(vel[lo[2]:lo[2] + n + 1, lo[1]:lo[1] + n + 1, lo[0]:lo[0] + n + 1])
-    p = Pair(vc, npml, "fp32")
+    p = Pair(vc, npml, precision)
     Nt = n + 2 * npml
     s_loc = tuple(int(v) for v in src - lo + npml)
     f = point_source((Nt, Nt, Nt), s_loc, H)
@@ -540,7 +541,7 @@ def test_c2_crop_solution_fp32(c2):
     u6, its6, rel6, st6 = p.o.solve(f, 1e-6)
     err = rel(to_np(u), uo)
     err6 = rel(u6, uo)
-    print(f"\nC2-crop FP32: |u_gpu - u_ref|/|u_ref| = {err:.3e} ({its} PC calls, relres {relres:.2e}); "
+    print(f"\nC2-crop {precision}: |u_gpu - u_ref|/|u_ref| = {err:.3e} ({its} PC calls, relres {relres:.2e}); "
           f"oracle at 1e-6: {err6:.3e} ({its6} calls); reference {its_o} calls to {rel_o:.1e}")
     assert err <= 1e-5, (err, err6)
 
