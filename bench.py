@@ -78,10 +78,62 @@ def recorded_traffic(nodes):
         return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of this process's later parallel regions (the oracle's)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def crop_parity(vel, omega, table, src, precision, crop=64):
+    """The benchmark's physics on a crop^3 box around its source (+ N_PML PML cells):
+    the GPU solve (this precision, tol 1e-6) against the FP64 oracle solved to 1e-10,
+    relative l2 over every node."""
+    import torch
+    from oracle.oracle import Hierarchy as OracleHierarchy
+    from paper_2608_22946_amd import helm
+    from workloads import point_source
+    sp = np.array(src) - N_PML
+    lo = np.clip(sp - crop // 2, 0, N_PHYS - crop)
+    vc = np.ascontiguousarray(vel[lo[2]:lo[2] + crop + 1, lo[1]:lo[1] + crop + 1, lo[0]:lo[0] + crop + 1])
+    Nc = crop + 2 * N_PML
+    s_loc = tuple(int(v) for v in sp - lo + N_PML)
+    fc = point_source((Nc, Nc, Nc), s_loc, H)
+    # the crop has its own minimum velocity; the frequency stays the benchmark's
+    Hc = helm.Hierarchy(torch.from_numpy(vc), H, omega, N_PML, precision=precision, table=table, device="cuda:0")
+    cdt = np.complex128 if precision == "fp64" else np.complex64
+    uc, its, rel, rc = Hc.solve(torch.from_numpy(fc.astype(cdt)).cuda(), TOL)
+    ug = uc.cpu().numpy().astype(np.complex128)
+    Hc.close()
+    O = OracleHierarchy(vc, H, omega, N_PML, table)
+    t0 = time.perf_counter()
+    uo, its_o, rel_o, st = O.solve(fc, 1e-10)
+    t_o = time.perf_counter() - t0
+    O.close()
+    return {"crop": f"{crop}^3 + {N_PML} PML around the benchmark source, the benchmark's omega",
+            "rel_l2_error": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)), "gpu_pc_calls": int(its),
+            "oracle_tol": 1e-10, "oracle_pc_calls": int(its_o), "oracle_s": round(t_o, 1)}
+
+
 def cpu_baseline(vel, omega, table, gpu_pc_calls):
     """The FP64 oracle on the host cores: one preconditioner
     application (Algorithm 1) on the full workload, scaled to seconds per
-    right-hand side by the GPU run's preconditioner-call count."""
+    right-hand side by the GPU run's preconditioner-call count; beside it one
+    FP64 A_h apply at the full size on all threads and on one thread."""
     from oracle.oracle import Hierarchy as OracleHierarchy
     from workloads import random_complex
     O = OracleHierarchy(vel, H, omega, N_PML, table)
@@ -91,11 +143,23 @@ def cpu_baseline(vel, omega, table, gpu_pc_calls):
     t0 = time.perf_counter()
     O.precond(r)
     t_pc = time.perf_counter() - t0
-    O.close()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    O.apply(0, 0, r)
+    t_ap = time.perf_counter() - t0
+    single = None
+    if _omp_threads(1):
+        t0 = time.perf_counter()
+        O.apply(0, 0, r)
+        single = time.perf_counter() - t0
+        _omp_threads(cores)
+    O.close()
     return {"value": t_pc * gpu_pc_calls, "unit": "s per RHS (extrapolated)", "cores": cores, "kind": "oracle",
             "sample": f"one FP64 preconditioner application (Algorithm 1) on the full 352^3 workload took "
-                      f"{t_pc:.2f} s; scaled by the GPU solve's {gpu_pc_calls} preconditioner calls"}
+                      f"{t_pc:.2f} s; scaled by the GPU solve's {gpu_pc_calls} preconditioner calls",
+            "cpu_model": cpu_model(),
+            "apply_s": {"sample": "one FP64 A_h apply on the full 352^3 grid", "threads": cores,
+                        "s": round(t_ap, 3), "single_thread_s": None if single is None else round(single, 3)}}
 
 
 def green_err(u, N, npml, h, k, src):
@@ -499,6 +563,16 @@ def main():
     t_apply = ev0.elapsed_time(ev1) / 1e3 / args.apply_reps
     alg_bytes = per_node * nodes[0]
     achieved = alg_bytes / t_apply / 1e9
+    # device copy of one fine vector (read + write) on the same stream: the practical streaming rate
+    zc = torch.empty_like(x)
+    zc.copy_(x)
+    ev0.record(stream)
+    for _ in range(20):
+        zc.copy_(x)
+    ev1.record(stream)
+    ev1.synchronize()
+    copy_gbs = 2 * x.numel() * x.element_size() / (ev0.elapsed_time(ev1) / 1e3 / 20) / 1e9
+    del zc
     if args.profile_apply:
         # the fused two-sweep Jacobi from zero on the fine level (A_h, omega_h 0.8), then a plain copy
         # of known size for counter calibration
@@ -570,7 +644,8 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(t_apply * 1e3, 4)},
+                     "avg_launch_ms": round(t_apply * 1e3, 4),
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "pc_calls": int(its),
         "relres": float(rel),
         "solve_per_pc_ms": round(ms_step / max(int(its), 1), 2),
@@ -579,6 +654,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(vel, omega, table, int(its))
+        out["parity_vs_oracle"] = crop_parity(vel, omega, table, src, args.precision)
     print(json.dumps(out), flush=True)
 
 
