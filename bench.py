@@ -78,6 +78,9 @@ def recorded_traffic(nodes):
         return None
 
 
+# ---- the cpu_baseline leg: the only code in this file that runs the FP64 oracle (a checker and a
+# ---- baseline, never part of the solve); skipped with --no-cpu-baseline
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -160,6 +163,40 @@ def cpu_baseline(vel, omega, table, gpu_pc_calls):
             "cpu_model": cpu_model(),
             "apply_s": {"sample": "one FP64 A_h apply on the full 352^3 grid", "threads": cores,
                         "s": round(t_ap, 3), "single_thread_s": None if single is None else round(single, 3)}}
+
+
+def c4_crop_parity(vel, omega, table, src, npml, precision, crop, crop_tol):
+    """The 800^3 workload's physics on a crop^3 + npml box around its source: the GPU
+    solve (this precision, tol 1e-6) against the FP64 oracle solved to crop_tol."""
+    import torch
+    from oracle.oracle import Hierarchy as OracleHierarchy
+    from paper_2608_22946_amd import helm
+    from workloads import point_source
+    n = vel.shape[0] - 1
+    dev = torch.device("cuda", 0)
+    sp = np.array(src) - npml
+    lo = np.clip(sp - crop // 2, 0, n - crop)
+    vc = np.ascontiguousarray(vel[lo[2]:lo[2] + crop + 1, lo[1]:lo[1] + crop + 1, lo[0]:lo[0] + crop + 1])
+    Nc = crop + 2 * npml
+    s_loc = tuple(int(v) for v in sp - lo + npml)
+    fc = point_source((Nc, Nc, Nc), s_loc, H)
+    Hc = helm.Hierarchy(torch.from_numpy(vc), H, omega, npml, precision=precision, table=table, device=dev)
+    uc, its_c, rel_c, rc_c = Hc.solve(torch.from_numpy(fc.astype(np.complex128 if precision == "fp64"
+                                                                     else np.complex64)).to(dev), TOL)
+    ug = uc.cpu().numpy().astype(np.complex128)
+    Hc.close()
+    t0 = time.perf_counter()
+    O = OracleHierarchy(vc, H, omega, npml, table)
+    uo, its_o, rel_o, st_o = O.solve(fc, crop_tol)
+    t_or = time.perf_counter() - t0
+    O.close()
+    err = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+    return {"c4": "crop", "crop": f"{crop}^3 + {npml} PML around the source", "precision": precision,
+            "gpu_pc_calls": int(its_c), "gpu_relres": float(rel_c), "oracle_pc_calls": its_o,
+            "oracle_relres": rel_o, "oracle_s": round(t_or, 1), "rel_l2_error_vs_oracle": err}
+
+
+# ---- end of the cpu_baseline leg
 
 
 def green_err(u, N, npml, h, k, src):
@@ -292,15 +329,15 @@ def c4_source(vel, npml, seed=4):
             return tuple(int(v) + npml for v in p)
 
 
-def c4_bench(precision, apply_reps, crop, crop_tol):
+def c4_bench(precision, apply_reps, crop, crop_tol, with_cpu):
     """Largest single-GPU workload: 768^3 + 16 PML cells (800^3 total, 5.1e8 nodes),
     1500 m/s background with a seeded ellipsoidal 4500 m/s inclusion (semi-axes
     150/120/90 cells) times (1 + 0.1 g), g a GRF of correlation length 20 cells, 6
     points per wavelength at the minimum velocity, one seeded source outside the
     inclusion, tol 1e-6.  One warm-up and one timed solve; the fine A_h apply timed
-    at this shape; then (crop > 0) the same physics on a crop^3 + 16 PML box around
-    the source, solved on the GPU to 1e-6 and by the FP64 oracle to crop_tol, compared
-    node by node.  One JSON line."""
+    at this shape; then, as the cpu_baseline leg (crop > 0, with_cpu), the same physics
+    on a crop^3 + 16 PML box around the source, solved on the GPU to 1e-6 and by the
+    FP64 oracle to crop_tol, compared node by node."""
     import torch
     from paper_2608_22946_amd import helm
     from workloads import ellipsoid_grf_velocity, load_iofd_table, point_source
@@ -365,32 +402,8 @@ def c4_bench(precision, apply_reps, crop, crop_tol):
     Hh.close()
     del Hh, f, u
     torch.cuda.empty_cache()
-    if crop <= 0:
-        return
-    # ---- the same physics on a crop around the source: GPU (this precision) vs the FP64 oracle ----
-    from oracle.oracle import Hierarchy as OracleHierarchy
-    sp = np.array(src) - npml
-    lo = np.clip(sp - crop // 2, 0, n - crop)
-    vc = np.ascontiguousarray(vel[lo[2]:lo[2] + crop + 1, lo[1]:lo[1] + crop + 1, lo[0]:lo[0] + crop + 1])
-    del vel
-    Nc = crop + 2 * npml
-    s_loc = tuple(int(v) for v in sp - lo + npml)
-    fc = point_source((Nc, Nc, Nc), s_loc, H)
-    Hc = helm.Hierarchy(torch.from_numpy(vc), H, omega, npml, precision=precision, table=table, device=dev)
-    uc, its_c, rel_c, rc_c = Hc.solve(torch.from_numpy(fc.astype(np.complex128 if precision == "fp64"
-                                                                     else np.complex64)).to(dev), TOL)
-    ug = uc.cpu().numpy().astype(np.complex128)
-    Hc.close()
-    t0 = time.perf_counter()
-    O = OracleHierarchy(vc, H, omega, npml, table)
-    uo, its_o, rel_o, st_o = O.solve(fc, crop_tol)
-    t_or = time.perf_counter() - t0
-    O.close()
-    err = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
-    print(json.dumps({"c4": "crop", "crop": f"{crop}^3 + {npml} PML around the source", "precision": precision,
-                      "gpu_pc_calls": int(its_c), "gpu_relres": float(rel_c), "oracle_pc_calls": its_o,
-                      "oracle_relres": rel_o, "oracle_s": round(t_or, 1),
-                      "rel_l2_error_vs_oracle": err}), flush=True)
+    if crop > 0 and with_cpu:
+        print(json.dumps(c4_crop_parity(vel, omega, table, src, npml, precision, crop, crop_tol)), flush=True)
 
 
 def grad_bench(steps, warmup, apply_reps, with_cpu):
@@ -522,7 +535,7 @@ def main():
         grad_bench(args.steps, args.warmup, args.apply_reps, not args.no_cpu_baseline)
         return
     if args.c4:
-        c4_bench(args.precision, args.apply_reps, args.crop, args.crop_tol)
+        c4_bench(args.precision, args.apply_reps, args.crop, args.crop_tol, not args.no_cpu_baseline)
         return
 
     import torch
