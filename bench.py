@@ -497,6 +497,108 @@ def grad_bench(steps, warmup, apply_reps, with_cpu):
     print(json.dumps(out), flush=True)
 
 
+def c5_bench(n_dirs=8):
+    """Misfit gradient on the 216^3 workload (192^3 + 12 PML cells): GRF velocity (seed 5),
+    the true model times (1 + 0.05 exp(-r^2 / (2 * 15^2))) around the box centre (r in cells),
+    16 point sources at physical (24 + 48 i, 24 + 48 j, 15), receivers at every physical (x, y)
+    node of the plane z = 20, synthetic data from the true model (FP64 solves to 1e-12),
+    J = 1/2 sum |u - d|^2 over receivers and sources, 6 points per wavelength at the smaller
+    c_min.  Times the FP32 gradient (forward solves with checkpoint, then adjoint solves and
+    assembly; tol 1e-6) and checks the FP64 gradient (tol 1e-12) against central differences of J
+    along n_dirs seeded smooth velocity directions (max 0.05 m/s).  JSON lines per direction,
+    then a summary."""
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import grf_velocity, load_iofd_table, point_source
+    from workloads.configs import omega_for_ppw
+    from workloads.media import gaussian_random_field
+
+    n, npml = 192, 12
+    N = n + 2 * npml
+    vel0 = grf_velocity(n, n, n, seed=5)
+    ax = np.arange(n + 1, dtype=np.float64) - n / 2
+    r2 = ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+    vel_true = (vel0 * (1.0 + 0.05 * np.exp(-r2 / (2 * 15.0 ** 2)))).astype(np.float32)
+    del r2
+    omega = omega_for_ppw(float(min(vel0.min(), vel_true.min())), H)
+    srcs = [(npml + 24 + 48 * i, npml + 24 + 48 * j, npml + 15) for j in range(4) for i in range(4)]
+    zr = npml + 20
+    rec = (slice(None), zr, slice(npml, npml + n + 1), slice(npml, npml + n + 1))
+    table = load_iofd_table()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    F64 = torch.from_numpy(np.stack([point_source((N, N, N), sp, H) for sp in srcs])).to(dev)
+    F32 = F64.to(torch.complex64)
+
+    def hier(vel, prec):
+        return helm.Hierarchy(torch.from_numpy(np.ascontiguousarray(vel)), H, omega, npml, precision=prec,
+                              table=table, device=dev)
+
+    Ht = hier(vel_true, "fp64")
+    d = Ht.solve(F64, 1e-12)[0][rec].clone()
+    Ht.close()
+
+    def misfit(vel):
+        Hm = hier(vel, "fp64")
+        u, its, rel, rc = Hm.solve(F64, 1e-12)
+        Hm.close()
+        return 0.5 * float((u[rec] - d).abs().pow(2).sum())
+
+    def gradient(prec, tol):
+        Hg = hier(vel0, prec)
+        F = F64 if prec == "fp64" else F32
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, v, its_f, rel_f, rc = Hg.solve_checkpoint(F, tol)
+        s = torch.zeros_like(F)
+        s[rec] = u[rec] - d.to(F.dtype)
+        gm, its, rel, rc2 = Hg.grad(F, s, tol, v=v)
+        gc = Hg.grad_to_velocity(gm)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out = gc.double().cpu().numpy()
+        Hg.close()
+        return out, t, int(np.sum(its_f)), int(np.sum(its[:, 1]))
+
+    g32, t32, pf32, pa32 = gradient("fp32", 1e-6)
+    g32, t32, pf32, pa32 = gradient("fp32", 1e-6)   # the second run reuses the timed tiling
+    g64, t64, pf64, pa64 = gradient("fp64", 1e-12)
+    J0 = misfit(vel0)
+    checks = []
+    for k in range(n_dirs):
+        # m/s, smooth, max |dc| = 0.05: a phase change of a few 1e-3 rad over the ~30 wavelengths of the
+        # box keeps J near its linear range (10 m/s moved phases by ~1 rad).  The data residual is only
+        # ~1e-4 of |d| here, so the cubic term of J still biases a central difference by O(dc^2):
+        # steps dc and dc / 2 and their Richardson extrapolation (4 D(dc/2) - D(dc)) / 3 remove it.
+        dc = 0.05 * gaussian_random_field(n, n, n, 15.0, 500 + k)
+        cd, ad = [], []
+        for scale in (1.0, 0.5):
+            vp = (vel0 + scale * dc).astype(np.float32)
+            vm = (vel0 - scale * dc).astype(np.float32)
+            jp, jm = misfit(vp), misfit(vm)
+            cd.append((jp - jm) / 2.0)
+            # the velocities evaluated are FP32-rounded: project onto the perturbation actually taken
+            ad.append(float(np.sum(g64 * (vp.astype(np.float64) - vm.astype(np.float64)))) / 2.0)
+        # the adjoint values for dc and dc / 2 differ only by the rounding of the perturbed velocities
+        rich = (4.0 * cd[1] / ad[1] - cd[0] / ad[0]) / 3.0   # extrapolated ratio central difference / adjoint
+        checks.append({"dir": k, "central_difference": cd[0], "adjoint": ad[0],
+                       "rel_diff": abs(ad[0] - cd[0]) / abs(cd[0]),
+                       "rel_diff_half_step": abs(ad[1] - cd[1]) / abs(cd[1]),
+                       "rel_diff_richardson": abs(rich - 1.0)})
+        print(json.dumps({"c5": "direction", **checks[-1]}), flush=True)
+    out = {"c5": "gradient", "workload": "grf-216-grad: 192^3 + 12 PML, GRF seed 5 x (1 + 0.05 Gaussian blob), "
+                                        "16 sources, receivers on z = 20, J = 1/2 sum |u - d|^2",
+           "nodes_fine": int(N + 1) ** 3, "misfit": J0,
+           "data_residual_rel": float(np.sqrt(2 * J0) / float(d.abs().pow(2).sum().sqrt())),
+           "fp32_gradient_s": round(t32, 3), "fp32_pc_calls_forward": pf32, "fp32_pc_calls_adjoint": pa32,
+           "fp64_gradient_s": round(t64, 3), "fp64_pc_calls_forward": pf64, "fp64_pc_calls_adjoint": pa64,
+           "fp32_vs_fp64_gradient_rel_l2": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)),
+           "fd_check_max_rel_diff": max(c["rel_diff"] for c in checks),
+           "fd_check_max_rel_diff_richardson": max(c["rel_diff_richardson"] for c in checks),
+           "fd_directions": len(checks)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -515,6 +617,8 @@ def main():
                     help="run the 64-source 288^3 layered workload with 1, 2 and 4 concurrent lanes instead")
     ap.add_argument("--grad", action="store_true",
                     help="time the adjoint misfit gradient on the benchmark workload instead")
+    ap.add_argument("--c5", action="store_true",
+                    help="run the 216^3 misfit-gradient workload with its central-difference check instead")
     ap.add_argument("--c4", action="store_true",
                     help="run the 800^3 ellipsoid workload (largest single-GPU case) instead")
     ap.add_argument("--crop", type=int, default=128,
@@ -533,6 +637,9 @@ def main():
         return
     if args.grad:
         grad_bench(args.steps, args.warmup, args.apply_reps, not args.no_cpu_baseline)
+        return
+    if args.c5:
+        c5_bench()
         return
     if args.c4:
         c4_bench(args.precision, args.apply_reps, args.crop, args.crop_tol, not args.no_cpu_baseline)
