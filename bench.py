@@ -278,6 +278,36 @@ def paper_table():
         del Hh
 
 
+def green_pml(cases=((0, 1.119058), (1, 1.119058), (2, 1.119058), (0, 1.5), (0, 2.0), (0, 3.0))):
+    """The 512^3 Green-function case of the paper's table (8 PML cells, c = 1, 6 points per
+    wavelength, FP32, tol 1e-4) under the alternative readings of the PML profile
+    (helm_options.pml_variant) and for several gamma_max: one JSON line each with Err."""
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import homogeneous, load_iofd_table, point_source
+    from workloads.configs import omega_for_ppw
+
+    Ntot, npml = 512, 8
+    n = Ntot - 2 * npml
+    h = 1.0 / n
+    src = (Ntot // 2,) * 3
+    dev = torch.device("cuda", 0)
+    table = load_iofd_table()
+    f = torch.from_numpy(point_source((Ntot,) * 3, src, h, dtype=np.complex64)).to(dev)
+    vel = homogeneous(n, n, n, 1.0)
+    omega = omega_for_ppw(1.0, h)
+    for variant, gmax in cases:
+        Hh = helm.Hierarchy(torch.from_numpy(vel), h, omega, npml, precision="fp32", table=table, device=dev,
+                            pml_variant=variant, gamma_max=gmax)
+        u, its, rel, rc = Hh.solve(f, 1e-4)
+        err = float(green_err(u.cpu().numpy(), Ntot, npml, h, omega, src))
+        Hh.close()
+        del Hh, u
+        print(json.dumps({"case": "green-pml", "mesh": f"{Ntot}^3", "n_pml": npml, "tol": 1e-4,
+                          "pml_variant": variant, "gamma_max": gmax, "pc_calls": int(its), "err": err,
+                          "paper_a100_err": 2.4936e-3}), flush=True)
+
+
 def multi_rhs(lane_counts=(1, 2, 4), seed=3):
     """Many right-hand sides on one hierarchy: 256^3 + 16-cell PML (288^3 total), a seeded
     8-layer model (1500..4000 m/s, sharp interfaces), 64 point sources on an 8 x 8 grid in
@@ -617,6 +647,8 @@ def main():
                     help="run the 64-source 288^3 layered workload with 1, 2 and 4 concurrent lanes instead")
     ap.add_argument("--grad", action="store_true",
                     help="time the adjoint misfit gradient on the benchmark workload instead")
+    ap.add_argument("--green-pml", action="store_true",
+                    help="run the 512^3 Green-function case under the alternative PML readings instead")
     ap.add_argument("--c5", action="store_true",
                     help="run the 216^3 misfit-gradient workload with its central-difference check instead")
     ap.add_argument("--c4", action="store_true",
@@ -640,6 +672,9 @@ def main():
         return
     if args.c5:
         c5_bench()
+        return
+    if args.green_pml:
+        green_pml()
         return
     if args.c4:
         c4_bench(args.precision, args.apply_reps, args.crop, args.crop_tol, not args.no_cpu_baseline)

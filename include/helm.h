@@ -109,9 +109,17 @@ typedef struct {
     int lanes;                /* right-hand sides helm_solve runs concurrently (1..8; 0 = 1), each on
                                  its own copy of the solver's vectors and its own stream; the
                                  workspace grows by one copy per lane */
+    int pml_variant;          /* reading of eq. pml-profile / eq. pml-second-difference (default 0):
+                                 0 = gamma at the nodes from the distance d to the physical box with
+                                     L_pml = n_pml h (gamma_max at the Dirichlet nodes), half-node gamma
+                                     the mean of the two node values;
+                                 1 = as 0, but half-node gamma from the half-node distance;
+                                 2 = as 0, but the profile reaches gamma_max one fine cell earlier
+                                     (denominator L_pml - h) and stays there.
+                                 1 and 2 exist to study the Green-function error; the hot path is the same. */
 } helm_options;
 
-/* Fill *opt with the defaults above (table NULL, stream NULL, FP32). */
+/* Fill *opt with the defaults above (table NULL, stream NULL, FP32, pml_variant 0). */
 helm_status helm_default_options(helm_options *opt);
 
 /* Bytes of device workspace helm_setup needs for this grid and options

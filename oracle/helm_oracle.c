@@ -39,6 +39,7 @@ enum { OP_A = 0, OP_B = 1, OP_Q = 2, OP_DIAG_A = 3, OP_DIAG_B = 4 };
 typedef struct {
     double sigma, omega_h, omega_2h, omega_4h, gamma_max;
     int nJ_h, nJ_2h, nJ_4h, m_h, c_2h, m_2h, m_4h, m_out;
+    int pml_variant;   /* 0: the reading used throughout; 1, 2: alternatives (pml_gamma) */
 } or_params;
 
 typedef struct {
@@ -161,16 +162,21 @@ static void row_coeffs(const or_hier *H, double c, double ell, double *kappa, do
 /* PML stretching (eq. pml-profile)                                    */
 /* ------------------------------------------------------------------ */
 
+/* gamma(d) = gamma_max (1 - cos(pi d / (2 L_pml))), d the distance from the physical box
+ * into the layer, L_pml = n_pml h.  Alternative readings (pml_variant): 2 = the profile
+ * reaches gamma_max at d = L_pml - h and stays there; 1 only changes the half nodes
+ * (level_init). */
 static double pml_gamma(const or_hier *H, int axis, double x)
 {
     double Lpml = H->n_pml * H->h;
     if (Lpml <= 0) return 0.0;
     double L = H->lev[0].n[axis] * H->h;         /* total box length on this axis */
+    double Lp = (H->p.pml_variant == 2) ? Lpml - H->h : Lpml;
     double d = 0.0;
     if (x < Lpml) d = Lpml - x;
     if (x > L - Lpml) d = x - (L - Lpml);
-    if (d > Lpml) d = Lpml;
-    return H->p.gamma_max * (1.0 - cos(M_PI * d / (2.0 * Lpml)));
+    if (d > Lp) d = Lp;
+    return H->p.gamma_max * (1.0 - cos(M_PI * d / (2.0 * Lp)));
 }
 
 static int level_init(or_hier *H, int li, const double *vel_phys, const int nphys[3])
@@ -198,7 +204,8 @@ static int level_init(or_hier *H, int li, const double *vel_phys, const int nphy
                     vel_phys[((size_t)pi[2] * (nphys[1] + 1) + pi[1]) * (nphys[0] + 1) + pi[0]];
             }
     /* 1/xi at nodes and at half nodes; the half-node gamma is the average of the
-     * two adjacent node values, inverted afterwards (Sec. 2.2) */
+     * two adjacent node values, inverted afterwards (Sec. 2.2; pml_variant 1: gamma
+     * at the half node itself) */
     for (int a = 0; a < 3; ++a) {
         int n = L->n[a];
         L->xin[a] = vnew((size_t)n + 1);
@@ -206,7 +213,9 @@ static int level_init(or_hier *H, int li, const double *vel_phys, const int nphy
         if (!L->xin[a] || !L->xih[a]) return OR_ENOMEM;
         for (int j = 0; j <= n; ++j) L->xin[a][j] = 1.0 / (1.0 + I * pml_gamma(H, a, j * L->ell));
         for (int j = 0; j < n; ++j) {
-            double g = 0.5 * (pml_gamma(H, a, j * L->ell) + pml_gamma(H, a, (j + 1) * L->ell));
+            double g = (H->p.pml_variant == 1)
+                           ? pml_gamma(H, a, (j + 0.5) * L->ell)
+                           : 0.5 * (pml_gamma(H, a, j * L->ell) + pml_gamma(H, a, (j + 1) * L->ell));
             L->xih[a][j] = 1.0 / (1.0 + I * g);
         }
     }
@@ -786,7 +795,7 @@ static void precond(const or_hier *H, const cplx *r, cplx *z)
 /* ------------------------------------------------------------------ */
 
 /* params: sigma, omega_h, omega_2h, omega_4h, gamma_max, nJ_h, nJ_2h, nJ_4h,
- *         m_h, c_2h, m_2h, m_4h, m_out  (13 doubles) */
+ *         m_h, c_2h, m_2h, m_4h, m_out, pml_variant  (14 doubles) */
 int or_create(const float *vel_phys, int nx, int ny, int nz, double h, double omega, int n_pml,
               const double *table, int K, double eta_max, const double *params, void **out)
 {
@@ -816,6 +825,7 @@ int or_create(const float *vel_phys, int nx, int ny, int nz, double h, double om
     H->p.m_2h = (int)params[10];
     H->p.m_4h = (int)params[11];
     H->p.m_out = (int)params[12];
+    H->p.pml_variant = (int)params[13];
     for (int a = 0; a < 3; ++a) H->lev[0].n[a] = N[a];
     int nphys[3] = {nx, ny, nz};
     for (int a = 0; a < 3; ++a) H->nphys[a] = nphys[a];

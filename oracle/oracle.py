@@ -20,9 +20,9 @@ OP_A, OP_B, OP_Q, OP_DIAG_A, OP_DIAG_B = 0, 1, 2, 3, 4
 
 # Fixed solver configuration of the paper's performance table.
 DEFAULT_PARAMS = dict(sigma=0.9, omega_h=0.8, omega_2h=0.8, omega_4h=0.2, gamma_max=1.119058,
-                      nJ_h=2, nJ_2h=2, nJ_4h=2, m_h=2, c_2h=2, m_2h=10, m_4h=4, m_out=5)
+                      nJ_h=2, nJ_2h=2, nJ_4h=2, m_h=2, c_2h=2, m_2h=10, m_4h=4, m_out=5, pml_variant=0)
 _PARAM_ORDER = ["sigma", "omega_h", "omega_2h", "omega_4h", "gamma_max", "nJ_h", "nJ_2h", "nJ_4h",
-                "m_h", "c_2h", "m_2h", "m_4h", "m_out"]
+                "m_h", "c_2h", "m_2h", "m_4h", "m_out", "pml_variant"]
 
 
 def build(force=False):

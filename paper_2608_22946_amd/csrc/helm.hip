@@ -204,19 +204,25 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
 // averaged to the half nodes before inversion; second-difference weights
 // wm = -xi_a^-1 xi_{a-1/2}^-1, wc = xi_a^-1 (xi_{a+1/2}^-1 + xi_{a-1/2}^-1),
 // wp = -xi_a^-1 xi_{a+1/2}^-1 (eq. pml-second-difference).
-void axis_weights(int n, double ell, double L, double Lpml, double gmax, std::vector<double> &w, int &lo, int &hi) {
+// gamma of eq. pml-profile at coordinate x of an axis of length L (helm_options.pml_variant:
+// 2 = the profile reaches gamma_max at d = Lpml - h)
+double pml_gamma(double x, double L, double Lpml, double h, double gmax, int variant) {
+    if (Lpml <= 0) return 0.0;
+    double d = std::max(0.0, std::max(Lpml - x, x - (L - Lpml)));
+    const double Lp = (variant == 2) ? Lpml - h : Lpml;
+    d = std::min(d, Lp);
+    return gmax * (1.0 - std::cos(M_PI * d / (2.0 * Lp)));
+}
+
+void axis_weights(int n, double ell, double L, double Lpml, double h, double gmax, int variant,
+                  std::vector<double> &w, int &lo, int &hi) {
     std::vector<double> gam(n + 1);
-    for (int j = 0; j <= n; ++j) {
-        const double x = j * ell;
-        double d = 0.0;
-        if (Lpml > 0) {
-            d = std::max(0.0, std::max(Lpml - x, x - (L - Lpml)));
-            d = std::min(d, Lpml);
-            gam[j] = gmax * (1.0 - std::cos(M_PI * d / (2.0 * Lpml)));
-        } else {
-            gam[j] = 0.0;
-        }
-    }
+    for (int j = 0; j <= n; ++j) gam[j] = pml_gamma(j * ell, L, Lpml, h, gmax, variant);
+    // half-node gamma: the mean of the node values (variant 1: at the half-node distance)
+    auto half = [&](int j) {   // between nodes j and j + 1
+        return (variant == 1) ? pml_gamma((j + 0.5) * ell, L, Lpml, h, gmax, variant)
+                              : 0.5 * (gam[j] + gam[j + 1]);
+    };
     auto inv = [](double g, double &re, double &im) {   // 1 / (1 + i g)
         const double den = 1.0 + g * g;
         re = 1.0 / den;
@@ -226,8 +232,8 @@ void axis_weights(int n, double ell, double L, double Lpml, double gmax, std::ve
     for (int j = 1; j <= n - 1; ++j) {
         double nr, ni, pr, pi, mr, mi;
         inv(gam[j], nr, ni);
-        inv(0.5 * (gam[j] + gam[j + 1]), pr, pi);
-        inv(0.5 * (gam[j - 1] + gam[j]), mr, mi);
+        inv(half(j), pr, pi);
+        inv(half(j - 1), mr, mi);
         double *o = &w[6 * j];
         o[0] = -(nr * mr - ni * mi);
         o[1] = -(nr * mi + ni * mr);
@@ -775,6 +781,7 @@ helm_status check_options(const helm_options *o, std::string &msg) {
     if (!tz_ok) { msg = "tile_tz must be 0, 2, 4, 8, 16, 32 or 64"; return HELM_EINVAL; }
     if (!in(o->tile_split, -1, 1)) { msg = "tile_split must be -1, 0 or 1"; return HELM_EINVAL; }
     if (!in(o->lanes, 0, kMaxLanes)) { msg = "lanes must be in 0..8"; return HELM_EINVAL; }
+    if (!in(o->pml_variant, 0, 2)) { msg = "pml_variant must be 0, 1 or 2"; return HELM_EINVAL; }
     return HELM_OK;
 }
 
@@ -977,6 +984,10 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
     int N[3];
     helm_status st = check_options(opt, msg);
     if (st == HELM_OK) st = check_dims(nx, ny, nz, n_pml, N, msg);
+    if (st == HELM_OK && opt->pml_variant == 2 && n_pml < 2) {
+        msg = "pml_variant 2 needs n_pml >= 2";
+        st = HELM_EINVAL;
+    }
     if (st == HELM_OK && (!velocity || !out)) { msg = "velocity and out must not be NULL"; st = HELM_EINVAL; }
     if (st == HELM_OK && (!(h > 0) || !(omega > 0) || !std::isfinite(h) || !std::isfinite(omega))) {
         msg = "h and omega must be finite and positive";
@@ -1042,7 +1053,7 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
         Geom &g = H->geom[l];
         level_geom(N, l, h, g);
         for (int a = 0; a < 3; ++a) {
-            axis_weights(g.n[a], g.ell, N[a] * h, Lpml, opt->gamma_max, w, g.lo[a], g.hi[a]);
+            axis_weights(g.n[a], g.ell, N[a] * h, Lpml, h, opt->gamma_max, opt->pml_variant, w, g.lo[a], g.hi[a]);
             wfv.assign(w.begin(), w.end());
             if ((e = hipMemcpyAsync(H->wd[l][a], w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
                 (e = hipMemcpyAsync(H->wf[l][a], wfv.data(), wfv.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess ||

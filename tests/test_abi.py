@@ -110,7 +110,7 @@ def test_good_tile_options_accepted(L):
 @pytest.mark.parametrize("field,value", [("m_out", 0), ("m_2h", 13), ("m_4h", 9), ("nJ_h", 0), ("c_2h", 0),
                                          ("iofd_K", 0), ("omega_2h", -0.1), ("struct_size", 8), ("precision", 7),
                                          ("tile_tz", 3), ("tile_tz", 128), ("tile_split", 2), ("tile_split", -2),
-                                         ("lanes", 9), ("lanes", -1)])
+                                         ("lanes", 9), ("lanes", -1), ("pml_variant", 3), ("pml_variant", -1)])
 def test_bad_options_rejected(L, field, value):
     rc, _ = _ws(L, (24, 24, 24), 4, _opts(**{field: value}))
     assert rc == -1
@@ -138,6 +138,11 @@ def test_setup_validates_before_device_work(L):
     o3 = _opts()
     o3.iofd_table = bad.ctypes.data
     assert L.helm_setup(dummy, 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o3), dummy, 1 << 30, ctypes.byref(out)) == -1
+    # pml_variant 2 needs at least two PML cells
+    o4 = _opts(pml_variant=2)
+    o4.iofd_table = tab.ctypes.data
+    assert L.helm_setup(dummy, 24, 24, 24, 10.0, 1.0, 0, ctypes.byref(o4), dummy, 1 << 30, ctypes.byref(out)) == -1
+    assert b"pml_variant 2" in L.helm_last_error(None)
     # workspace too small, and misaligned
     assert L.helm_setup(dummy, 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o), dummy, 100, ctypes.byref(out)) == -2
     assert L.helm_setup(ctypes.c_void_p(0x1001), 24, 24, 24, 10.0, 1.0, 4, ctypes.byref(o), ctypes.c_void_p(0x1008),

@@ -232,6 +232,18 @@ def test_precond(pair):
     assert err <= pair.tol(1e-8, FP32_MAP_GATE), err
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_apply_pml_variants(variant):
+    """The alternative PML readings (helm_options.pml_variant) on every level against the
+    oracle built with the same reading (FP64, GRF velocity, 8 PML cells)."""
+    vel = grf_velocity(40, 24, 32, seed=17, corr_len=6.0)
+    p = Pair(vel, 8, "fp64", pml_variant=variant)
+    for level, op in [(0, 0), (1, 1), (2, 1)]:
+        x = p.rand(level, 230 + level)
+        err = rel(to_np(p.g.apply(level, op, p.dev(x))), p.o.apply(level, op, x.astype(complex)))
+        assert err <= 1e-12, (level, err)
+
+
 def test_random_table_apply_and_q():
     """A perturbed table (nonzero slopes everywhere, non-identity beta)."""
     vel = grf_velocity(56, 20, 28, seed=3, corr_len=5.0)

@@ -170,6 +170,32 @@ def test_pml_profile_values(oracle_lib, table):
     np.testing.assert_allclose(node2[2], node[4], rtol=1e-15)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_pml_profile_alternative_readings(oracle_lib, table, variant):
+    """The two alternative readings of eq. pml-profile / eq. pml-second-difference kept
+    for the Green-function study: (1) half-node gamma at the half node's own distance
+    instead of the mean of the node values; (2) the profile reaches gamma_max at
+    d = L_pml - h and stays there.  Values from the closed forms."""
+    gmax, npml, N = 1.119058, 8, 32
+    Hh = oracle_lib.Hierarchy(homogeneous(16, 16, 16, 1500.0), H, OMEGA_PPW6, npml, table,
+                              params=dict(gamma_max=gmax, pml_variant=variant))
+    node, half = Hh.xi_inv(0, 0)
+    gam = lambda v: (1 / v - 1).imag                     # noqa: E731
+    assert np.allclose(node[npml:N - npml + 1], 1.0, atol=0, rtol=0)
+    if variant == 1:
+        # half node between nodes 3 and 4: d = 4.5 h of L_pml = 8 h
+        np.testing.assert_allclose(gam(half[3]), gmax * (1 - np.cos(np.pi * 4.5 / 16)), rtol=1e-13)
+        np.testing.assert_allclose(gam(node[4]), gmax * (1 - np.cos(np.pi / 4)), rtol=1e-13)
+        # the physical side of the first PML cell: d = h / 2
+        np.testing.assert_allclose(gam(half[npml - 1]), gmax * (1 - np.cos(np.pi * 0.5 / 16)), rtol=1e-13)
+    else:
+        # L' = 7 h: node 4 has d = 4 h; nodes 1 and 0 (d >= 7 h) carry gamma_max
+        np.testing.assert_allclose(gam(node[4]), gmax * (1 - np.cos(np.pi * 4 / 14)), rtol=1e-13)
+        np.testing.assert_allclose(gam(node[1]), gmax, rtol=1e-13)
+        np.testing.assert_allclose(gam(node[0]), gmax, rtol=1e-13)
+        np.testing.assert_allclose(gam(half[3]), 0.5 * (gam(node[3]) + gam(node[4])), rtol=1e-13)
+
+
 def test_seven_point_reduction(oracle_lib):
     """(a1..a5) = (1, 0, 0, 1, 0) gives the textbook 7-point -Delta_h - k^2."""
     tab = constant_table([1.0, 0.0, 0.0, 1.0, 0.0])
