@@ -117,9 +117,15 @@ typedef struct {
                                  2 = as 0, but the profile reaches gamma_max one fine cell earlier
                                      (denominator L_pml - h) and stays there.
                                  1 and 2 exist to study the Green-function error; the hot path is the same. */
+    int batch;                /* right-hand sides each lane advances together in one set of launches
+                                 (1..8; 0 = 1): every kernel of the solve runs once for all of them
+                                 (the slot is the grid's y index), each with its own vectors and Krylov
+                                 states; the workspace grows by one solver copy per slot and lane.
+                                 Results equal those of solving each right-hand side alone. */
 } helm_options;
 
-/* Fill *opt with the defaults above (table NULL, stream NULL, FP32, pml_variant 0). */
+/* Fill *opt with the defaults above (table NULL, stream NULL, FP32, pml_variant 0, lanes 1,
+ * batch 1). */
 helm_status helm_default_options(helm_options *opt);
 
 /* Bytes of device workspace helm_setup needs for this grid and options
@@ -143,7 +149,8 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
 /* Solve A_h v = Q_h f and return u = Q_h v for nrhs right-hand sides
  * (eq. iofd-complete-system) with outer FGMRES(m_out) right preconditioned by
  * Algorithm 1, from v = 0, until ||A_h v - b|| / ||b|| <= tol recomputed with
- * FP64 arithmetic (eq. relative-residual).
+ * FP64 arithmetic (eq. relative-residual).  The right-hand sides are taken in
+ * groups of options.batch; options.lanes groups run concurrently.
  *   f, u    DEVICE [nrhs][total grid] precision vectors (may not alias)
  *   iters   HOST int[nrhs]: preconditioner calls per right-hand side
  *   relres  HOST double[nrhs]: final true relative residual

@@ -27,6 +27,11 @@ thread_local std::string g_thread_error;
 }
 
 constexpr int kMaxLanes = 8;   // right-hand sides solved concurrently by helm_solve
+constexpr int kMaxBatch = 8;   // right-hand sides one lane advances together (slots)
+static_assert(sizeof(KState) % sizeof(double) == 0, "KState strides are counted in doubles");
+constexpr int kKStateDoubles = (int)(sizeof(KState) / sizeof(double));
+// device and pinned host scratch of a lane: EPI_STORE results of every slot (2 kRedSlots doubles each)
+constexpr int kScratchDoubles = 2 * kRedSlots * kMaxBatch > 256 ? 2 * kRedSlots * kMaxBatch : 256;
 
 // Everything one solve writes: Krylov vectors of the three levels, solver
 // states, reduction buffers, pinned host copies and the stream it runs on.
@@ -43,8 +48,10 @@ struct Lane {
     KState *st_outer, *st_smooth, *st_k2h, *st_bottom, *st_hook;
     RedBuf rb;
     double *dscratch;     // small device result buffer (dots, velocity check)
-    KState *host_state;   // pinned host copy of a Krylov state
+    KState *host_state;   // pinned host copies of the Krylov states of the lane's slots
     double *host_scratch; // pinned host doubles
+    int nslot;            // right-hand sides the lane advances together (helm_options.batch)
+    long long pstride;    // doubles of reduction partials per slot
     hipStream_t s;        // lane 0: the caller's stream; others: created by helm_setup (default priority)
     bool own_stream;
     std::string err;
@@ -145,7 +152,10 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     auto vec = [&](int l) { return c.take<char>(es * (size_t)g[l].nn); };
     // the preconditioner's inner vectors: FP16-stored in HELM_MIXED
     const size_t es16 = (o.precision == HELM_MIXED) ? sizeof(c16) : es;
-    auto vec16 = [&](int l) { return c.take<char>(es16 * (size_t)g[l].nn); };
+    // a lane's vectors hold one copy per batched slot, slot s at s times the vector's length
+    const int B = (o.batch > 1) ? o.batch : 1;
+    auto lvec = [&](int l) { return c.take<char>(es * (size_t)g[l].nn * B); };
+    auto lvec16 = [&](int l) { return c.take<char>(es16 * (size_t)g[l].nn * B); };
     helm_hierarchy dummy;
     helm_hierarchy *Hp = H ? H : &dummy;
     for (int l = 0; l < 3; ++l) {
@@ -167,35 +177,38 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
     if (H) H->nlanes = nl;
     for (int li = 0; li < nl; ++li) {
         Lane &Ln = Hp->lane[li];
-        for (int j = 0; j <= o.m_out; ++j) Ln.Vout[j] = vec(0);
-        for (int j = 0; j < o.m_out; ++j) Ln.Zout[j] = vec(0);
-        for (int j = 0; j <= o.m_h; ++j) Ln.Vs[j] = vec(0);
-        for (int j = 0; j < o.m_h; ++j) Ln.Zs[j] = vec(0);
-        Ln.x64 = c.take<c64>(g[0].nn);
-        Ln.b64 = c.take<c64>(g[0].nn);
-        for (int j = 0; j <= o.m_2h; ++j) Ln.V2[j] = vec(1);
-        for (int j = 0; j < o.m_2h; ++j) Ln.Z2[j] = vec16(1);
-        Ln.e2 = vec(1);
-        Ln.r2 = vec(1);
-        Ln.vy = vec16(1);
-        Ln.vr = vec16(1);
-        for (int j = 0; j <= o.m_4h; ++j) Ln.P4[j] = vec16(2);
-        for (int j = 0; j < o.m_4h; ++j) Ln.Z4[j] = vec16(2);
-        Ln.e4 = vec16(2);
-        for (int l = 0; l < 3; ++l) Ln.tmp[l] = vec(l);
+        for (int j = 0; j <= o.m_out; ++j) Ln.Vout[j] = lvec(0);
+        for (int j = 0; j < o.m_out; ++j) Ln.Zout[j] = lvec(0);
+        for (int j = 0; j <= o.m_h; ++j) Ln.Vs[j] = lvec(0);
+        for (int j = 0; j < o.m_h; ++j) Ln.Zs[j] = lvec(0);
+        Ln.x64 = c.take<c64>(g[0].nn * B);
+        Ln.b64 = c.take<c64>(g[0].nn * B);
+        for (int j = 0; j <= o.m_2h; ++j) Ln.V2[j] = lvec(1);
+        for (int j = 0; j < o.m_2h; ++j) Ln.Z2[j] = lvec16(1);
+        Ln.e2 = lvec(1);
+        Ln.r2 = lvec(1);
+        Ln.vy = lvec16(1);
+        Ln.vr = lvec16(1);
+        for (int j = 0; j <= o.m_4h; ++j) Ln.P4[j] = lvec16(2);
+        for (int j = 0; j < o.m_4h; ++j) Ln.Z4[j] = lvec16(2);
+        Ln.e4 = lvec16(2);
+        for (int l = 0; l < 3; ++l) Ln.tmp[l] = lvec(l);
         for (int l = 0; l < 2; ++l)
-            Ln.wrest[l] = c.take<char>(es * (size_t)(g[l].n[2] / 2 + 1) * (g[l].n[1] + 1) * (g[l].n[0] / 2 + 1));
-        Ln.st_outer = c.take<KState>(1);
-        Ln.st_smooth = c.take<KState>(1);
-        Ln.st_k2h = c.take<KState>(1);
-        Ln.st_bottom = c.take<KState>(1);
+            Ln.wrest[l] = c.take<char>(es * (size_t)(g[l].n[2] / 2 + 1) * (g[l].n[1] + 1) * (g[l].n[0] / 2 + 1) * B);
+        Ln.st_outer = c.take<KState>(B);
+        Ln.st_smooth = c.take<KState>(B);
+        Ln.st_k2h = c.take<KState>(B);
+        Ln.st_bottom = c.take<KState>(B);
         Ln.st_hook = c.take<KState>(1);
         size_t np = (size_t)kRedBlocks * 2 * 48;
         for (int l = 0; l < 3; ++l)
             np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2], kTzCandidates[0]));
-        Ln.rb.partials = c.take<double>(np);
+        Ln.rb.partials = c.take<double>(np * B);
+        Ln.nslot = B;
+        Ln.pstride = (long long)np;
         Ln.rb.counter = c.take<unsigned>(64);
-        Ln.dscratch = c.take<double>(256);
+        // small results: 256 doubles, or 2 kRedSlots per slot for the batched norms of the outer solve
+        Ln.dscratch = c.take<double>(kScratchDoubles);
     }
     return c.off + 256;
 }
@@ -487,8 +500,10 @@ struct Eng {
     // fsol times qs, the inverse norm of the cycle's input (the K_2h state's vs0 for its
     // unnormalised first basis vector, 1 for the others).  Every V-cycle map is homogeneous
     // of degree one in its input, so these units keep the stored values near unit size.
-    Scale sres(int l, const double *qs) const { return {H->fres[l], qs}; }
-    Scale ssol(int l, const double *qs) const { return {H->fsol[l], qs}; }
+    // qs is a Krylov state's vs0 (one per batched slot) or the shared constant 1
+    int qstride(const double *qs) const { return qs == H->d_one ? 0 : kKStateDoubles; }
+    Scale sres(int l, const double *qs) const { return {H->fres[l], qs, qstride(qs)}; }
+    Scale ssol(int l, const double *qs) const { return {H->fsol[l], qs, qstride(qs)}; }
     static c16 *h16(void *p) { return static_cast<c16 *>(p); }
 
     template <typename TX, typename TG, typename TY>
@@ -653,6 +668,116 @@ struct Eng {
         return status;
     }
 
+    // Several right-hand sides (nb <= the lane's slots) in one set of launches: slot s solves
+    // f_s in its own copy of every vector and state.  The slots advance in lockstep through the
+    // outer FGMRES steps; a slot whose residual estimate reaches tol (or that breaks down or
+    // reaches max_outer) leaves the launch mask for the rest of the cycle, and a converged slot
+    // leaves it for good, so each slot performs exactly the arithmetic of a solve on its own.
+    helm_status solve_batch(const T *f, T *u, int nb, double tol, int *iters, double *relres, c64 *v_out) {
+        if (nb == 1) return solve_one(f, u, tol, iters, relres, v_out);
+        if (nb < 1 || nb > Ln->nslot || transposed) return fail(H, HELM_EINVAL, "invalid batch");
+        Batch bt;
+        bt.n = nb;
+        bt.mask = (1u << nb) - 1u;
+        bt.pstride = Ln->pstride;
+        BatchScope scope(bt);
+        HIP_TRY((launch_qapply<double, T, c64>(H->Ld[0], f, Ln->b64, s)));   // b = Q_h f
+        const helm_status status = solve_b64_batch(nb, tol, iters, relres);
+        cur_batch().mask = bt.mask;
+        if (status < 0) return status;
+        if (u) HIP_TRY((launch_qapply<double, c64, T>(H->Ld[0], Ln->x64, u, s)));   // u = Q_h v
+        if (v_out) HIP_TRY((launch_convert<c64, c64>(Ln->x64, v_out, nn(0), s)));
+        HIP_TRY(hipStreamSynchronize(s));
+        return status;
+    }
+
+    hipError_t read_states(const KState *st, int nb) {
+        HIP_CHK(hipMemcpyAsync(Ln->host_state, st, nb * sizeof(KState), hipMemcpyDeviceToHost, s));
+        return hipStreamSynchronize(s);
+    }
+
+    helm_status solve_b64_batch(int nb, double tol, int *iters, double *relres) {
+        const helm_options &o = H->opt;
+        const long long n = nn(0);
+        T *V[kMMax + 1], *Zp[kMMax];
+        for (int j = 0; j <= o.m_out; ++j) V[j] = v(Ln->Vout[j]);
+        for (int j = 0; j < o.m_out; ++j) Zp[j] = v(Ln->Zout[j]);
+        KState *st = Ln->st_outer;
+        const int max_outer = o.max_outer > 0 ? o.max_outer : 1000;
+        const unsigned all = cur_batch().mask;
+        auto use = [](unsigned m) { cur_batch().mask = m; };
+        // ||b|| of every slot (EPI_STORE: 2 kRedSlots doubles per slot)
+        HIP_TRY(launch_dots<c64>(nullptr, 0, Ln->b64, true, n, EPI_STORE, nullptr, 0, Ln->dscratch, Ln->rb, s));
+        HIP_TRY(hipMemcpyAsync(Ln->host_scratch, Ln->dscratch, nb * 2 * kRedSlots * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double bn[kMaxBatch];
+        int its[kMaxBatch], kk[kMaxBatch];
+        helm_status stat[kMaxBatch];
+        unsigned active = 0;
+        for (int q = 0; q < nb; ++q) {
+            bn[q] = std::sqrt(Ln->host_scratch[q * 2 * kRedSlots]);
+            its[q] = 0;
+            stat[q] = HELM_OK;
+            iters[q] = 0;
+            relres[q] = 0.0;
+            if (!(bn[q] == bn[q]) || bn[q] > 1e300) return fail(H, HELM_BREAKDOWN, "non-finite right-hand side");
+            if (bn[q] > 0.0) active |= 1u << q;
+        }
+        HIP_TRY(launch_fill_zero<c64>(Ln->x64, n, s));
+        while (active) {
+            // true residuals in FP64 arithmetic: r = b - A x
+            use(active);
+            HIP_TRY(outer_residual(V[0], st));
+            HIP_TRY(read_states(st, nb));
+            unsigned cyc = 0;
+            for (int q = 0; q < nb; ++q) {
+                if (!(active >> q & 1u)) continue;
+                const KState &hs = Ln->host_state[q];
+                if (hs.nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite residual");
+                relres[q] = hs.beta / bn[q];
+                iters[q] = its[q];
+                if (relres[q] <= tol) continue;
+                if (its[q] >= max_outer) {
+                    stat[q] = HELM_NOT_CONVERGED;
+                    continue;
+                }
+                cyc |= 1u << q;
+            }
+            active = cyc;
+            if (!cyc) break;
+            unsigned inc = cyc;   // slots still stepping in this cycle
+            for (int q = 0; q < nb; ++q) kk[q] = 0;
+            for (int k = 0; k < o.m_out && inc; ++k) {
+                use(inc);
+                HIP_TRY(precond(V[k], Zp[k]));
+                HIP_TRY(stencil(0, M_APPLY, false, 0.0, Zp[k], nullptr, nullptr, V[k + 1]));
+                HIP_TRY(arnoldi(0, V, k, st, k == o.m_out - 1));
+                HIP_TRY(read_states(st, nb));
+                for (int q = 0; q < nb; ++q) {
+                    if (!(inc >> q & 1u)) continue;
+                    ++its[q];
+                    kk[q] = k + 1;
+                    const KState &hs = Ln->host_state[q];
+                    if (hs.nonfinite) return fail(H, HELM_BREAKDOWN, "non-finite Krylov quantity");
+                    const double est = std::hypot(hs.g[k + 1][0], hs.g[k + 1][1]) / bn[q];
+                    if (est <= tol || hs.breakdown || its[q] >= max_outer) inc &= ~(1u << q);
+                }
+            }
+            // x += Z y per slot (each with its own number of columns)
+            for (int q = 0; q < nb; ++q) {
+                if (!(cyc >> q & 1u)) continue;
+                use(1u << q);
+                HIP_TRY((launch_combine<c64, T>(Ln->x64, (const T *const *)Zp, kk[q], n, st, true, false, s)));
+            }
+        }
+        use(all);
+        helm_status worst = HELM_OK;
+        for (int q = 0; q < nb; ++q)
+            if (stat[q] == HELM_NOT_CONVERGED) worst = HELM_NOT_CONVERGED;
+        return worst;
+    }
+
     // FP64 true residual r = b - op x64 into V0 (working precision), its norm into the state
     hipError_t outer_residual(T *V0, KState *st) {
         if (!transposed) {
@@ -782,6 +907,7 @@ helm_status check_options(const helm_options *o, std::string &msg) {
     if (!in(o->tile_split, -1, 1)) { msg = "tile_split must be -1, 0 or 1"; return HELM_EINVAL; }
     if (!in(o->lanes, 0, kMaxLanes)) { msg = "lanes must be in 0..8"; return HELM_EINVAL; }
     if (!in(o->pml_variant, 0, 2)) { msg = "pml_variant must be 0, 1 or 2"; return HELM_EINVAL; }
+    if (!in(o->batch, 0, kMaxBatch)) { msg = "batch must be in 0..8"; return HELM_EINVAL; }
     return HELM_OK;
 }
 
@@ -964,6 +1090,7 @@ helm_status helm_default_options(helm_options *o) {
     o->tile_tz = 0;
     o->tile_split = -1;
     o->lanes = 1;
+    o->batch = 1;
     return HELM_OK;
 }
 
@@ -1030,8 +1157,8 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
                 return bail(HELM_EHIP, std::string("lane stream: ") + hipGetErrorString(e));
             Ln.own_stream = true;
         }
-        if ((e = hipHostMalloc((void **)&Ln.host_state, sizeof(KState))) != hipSuccess ||
-            (e = hipHostMalloc((void **)&Ln.host_scratch, 64 * sizeof(double))) != hipSuccess)
+        if ((e = hipHostMalloc((void **)&Ln.host_state, sizeof(KState) * kMaxBatch)) != hipSuccess ||
+            (e = hipHostMalloc((void **)&Ln.host_scratch, kScratchDoubles * sizeof(double))) != hipSuccess)
             return bail(HELM_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
         // reduction counters start at zero
         if ((e = hipMemsetAsync(Ln.rb.counter, 0, 64 * sizeof(unsigned), s)) != hipSuccess)
@@ -1118,19 +1245,22 @@ static helm_status solve_impl(helm_hierarchy *H, const void *f, int nrhs, double
     if (f == u || v == f || v == u) return fail(H, HELM_EINVAL, "f, u and v must not alias");
     const size_t es = (H->prec == HELM_FP64) ? sizeof(c64) : sizeof(c32);
     const long long n = H->geom[0].nn;
-    auto one = [&](int lane, int r) {
+    // right-hand sides r .. r + cnt - 1 on one lane, cnt <= the lane's slots
+    auto one = [&](int lane, int r, int cnt) {
         const char *fr = static_cast<const char *>(f) + (size_t)r * n * es;
         char *ur = static_cast<char *>(u) + (size_t)r * n * es;
         c64 *vr = v ? static_cast<c64 *>(v) + (size_t)r * n : nullptr;
         return (H->prec == HELM_FP64)
-                   ? Eng<c64>(H, lane).solve_one((const c64 *)fr, (c64 *)ur, tol, iters + r, relres + r, vr)
-                   : Eng<c32>(H, lane).solve_one((const c32 *)fr, (c32 *)ur, tol, iters + r, relres + r, vr);
+                   ? Eng<c64>(H, lane).solve_batch((const c64 *)fr, (c64 *)ur, cnt, tol, iters + r, relres + r, vr)
+                   : Eng<c32>(H, lane).solve_batch((const c32 *)fr, (c32 *)ur, cnt, tol, iters + r, relres + r, vr);
     };
-    const int L = std::min(H->nlanes, nrhs);
+    const int B = H->lane[0].nslot;
+    const int chunks = (nrhs + B - 1) / B;
+    const int L = std::min(H->nlanes, chunks);
     if (L <= 1) {
         helm_status worst = HELM_OK;
-        for (int r = 0; r < nrhs; ++r) {
-            helm_status st = one(0, r);
+        for (int r = 0; r < nrhs; r += B) {
+            helm_status st = one(0, r, std::min(B, nrhs - r));
             if (st < 0) return st;
             if (st == HELM_NOT_CONVERGED) worst = st;
         }
@@ -1158,11 +1288,12 @@ static helm_status solve_impl(helm_hierarchy *H, const void *f, int nrhs, double
                 lane_st[li] = fail(H, HELM_EHIP, "lane thread could not select the device");
                 return;
             }
-            for (int r = next++; r < nrhs; r = next++) {
-                helm_status st = one(li, r);
+            for (int c = next++; c < chunks; c = next++) {
+                const int r = c * B;
+                helm_status st = one(li, r, std::min(B, nrhs - r));
                 if (st < 0) {
                     lane_st[li] = st;
-                    next = nrhs;   // stop handing out work
+                    next = chunks;   // stop handing out work
                     return;
                 }
                 if (st == HELM_NOT_CONVERGED) lane_st[li] = st;

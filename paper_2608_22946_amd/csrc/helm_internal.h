@@ -50,6 +50,7 @@ using c16 = cplx<_Float16>;
 struct Scale {
     float f;             // constant factor
     const double *qs;    // device scalar; null for vectors stored in FP32 / FP64
+    int qstride = 0;     // doubles between the scalars of batched slots (0: one scalar for all)
 };
 constexpr float kHalfMax = 65504.0f;   // largest finite FP16 value
 
@@ -154,6 +155,43 @@ struct RedBuf {
     double *partials;    // [kRedBlocks][kRedStride][2]
     unsigned *counter;   // zero between kernels
 };
+
+// Right-hand sides batched in one launch (helm_options.batch).  Slot s = blockIdx.y
+// owns its own copy of every vector (at s times the vector's length from the pointer
+// passed), its own Krylov state (st + s), reduction partials (partials + s * pstride)
+// and completion counter (counter + s).  Blocks of a slot outside the mask return at
+// once, before any barrier or ticket, so a slot that has converged costs nothing.
+struct Batch {
+    int n = 1;               // slots (gridDim.y)
+    unsigned mask = 1u;      // bit s set: slot s runs
+    long long pstride = 0;   // doubles between the slots' reduction partials
+};
+// The batch of the calling host thread's launches (1 slot unless a BatchScope is active):
+// the launchers read it, so the solver's code is the same for one and for several slots.
+Batch &cur_batch();
+struct BatchScope {
+    Batch saved;
+    explicit BatchScope(const Batch &b) : saved(cur_batch()) { cur_batch() = b; }
+    ~BatchScope() { cur_batch() = saved; }
+    BatchScope(const BatchScope &) = delete;
+    BatchScope &operator=(const BatchScope &) = delete;
+};
+
+// slot index sl: blockIdx.y in the 1-D and 2-D kernels, from blockIdx.z in the transfers
+__device__ __forceinline__ bool slot_off(const Batch &b, int sl) { return !((b.mask >> sl) & 1u); }
+__device__ __forceinline__ RedBuf slot_rb(RedBuf rb, const Batch &b, int sl) {
+    rb.partials += (long long)sl * b.pstride;
+    rb.counter += sl;
+    return rb;
+}
+template <typename T>
+__device__ __forceinline__ T *slot_ptr(T *p, long long stride, int sl) {
+    return p ? p + (long long)sl * stride : p;
+}
+__device__ __forceinline__ Scale slot_scale(Scale s, int sl) {
+    if (s.qs) s.qs += (long long)sl * s.qstride;
+    return s;
+}
 
 // M_RESID_R: residual restricted in x and z on the fly (first pass of the fused
 // residual + full weighting; launch_restrict_y finishes it)

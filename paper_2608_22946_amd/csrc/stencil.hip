@@ -15,7 +15,8 @@ template <typename R, typename TI, typename TO>
 hipError_t launch_qapply(const LevelArgs<R> &L, const TI *x, TO *y, hipStream_t s) {
     const long long nn = (long long)(L.nz + 1) * L.sy;
     int blocks = (int)std::min<long long>((nn + 255) / 256, 65536);
-    hipLaunchKernelGGL((k_qapply<R, TI, TO>), dim3(blocks), dim3(256), sizeof(R) * L.K * 12, s, L, x, y);
+    hipLaunchKernelGGL((k_qapply<R, TI, TO>), dim3(blocks, cur_batch().n), dim3(256), sizeof(R) * L.K * 12, s, L, x, y,
+                       cur_batch());
     return hipGetLastError();
 }
 
@@ -36,7 +37,8 @@ hipError_t launch_jac1(const LevelArgs<R> &L, int shifted, double omegaJ, const 
     if (!dinv) return hipErrorInvalidValue;
     const long long nn = (long long)(L.nz + 1) * L.sy;
     int blocks = (int)std::min<long long>((nn + 255) / 256, 65536);
-    hipLaunchKernelGGL((k_jac1<R, T>), dim3(blocks), dim3(256), 0, s, dinv, g, y, nn, (R)omegaJ);
+    hipLaunchKernelGGL((k_jac1<R, T>), dim3(blocks, cur_batch().n), dim3(256), 0, s, dinv, g, y, nn, (R)omegaJ,
+                       cur_batch());
     return hipGetLastError();
 }
 

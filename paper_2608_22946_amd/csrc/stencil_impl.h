@@ -642,7 +642,31 @@ struct TileMap {
 template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM, int PART>
 __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
                                                  const TY *__restrict__ base, TY *__restrict__ y, R omegaJ, TileMap M,
-                                                 RedBuf rb, KState *st, Scales sc) {
+                                                 RedBuf rb, KState *st, Scales sc, Batch bt) {
+    // XCD-aware order of (tile, slot) pairs: block b runs on XCD b % 8; each XCD takes a
+    // contiguous range of u = tile * slots + slot, so the slots of one tile run back to
+    // back on one XCD and share the tile's per-node values and D^-1 through its L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
+    const int u = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+    const int sl = u % bt.n;   // batched right-hand side: its own vectors, state and partials
+    int t = u / bt.n;
+    const int tile = t;
+    if (slot_off(bt, sl)) return;
+    {
+        const long long nn = (long long)(L.nz + 1) * L.sy;
+        x = slot_ptr(x, nn, sl);
+        g = slot_ptr(g, nn, sl);
+        base = slot_ptr(base, nn, sl);
+        // M_RESID_R writes the x/z-restricted rows [coarse z][fine y][coarse x]
+        y = slot_ptr(y, MODE == M_RESID_R ? (long long)((L.nz >> 1) + 1) * (L.ny + 1) * ((L.nx >> 1) + 1) : nn, sl);
+        st = slot_ptr(st, 1, sl);
+        rb = slot_rb(rb, bt, sl);
+        sc.x = slot_scale(sc.x, sl);
+        sc.g = slot_scale(sc.g, sl);
+        sc.b = slot_scale(sc.b, sl);
+        sc.y = slot_scale(sc.y, sl);
+    }
     const R mul[4] = {load_mul<R, TX>(sc.x), load_mul<R, TG>(sc.g), load_mul<R, TY>(sc.b), store_mul<R, TY>(sc.y)};
     extern __shared__ unsigned char smem_raw[];
     R *stab = reinterpret_cast<R *>(smem_raw);   // alpha pieces, then (FP32) the shell quintics
@@ -652,10 +676,6 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
         for (int i = tid; i < (L.K + 1) * 24; i += 256) stab[L.K * 20 + i] = L.ctab[i];
     __syncthreads();
 
-    // XCD-aware tile order: block b runs on XCD b % 8; give each XCD a contiguous tile range
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
-    int t = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
     const int ntx = M.ntx, nty = M.nty;
     int xt, yt, zc;
     if (PART == 0) {
@@ -758,7 +778,7 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
                                                                   out_lane, nrm);
     }
     if (NORM) {
-        block_reduce_store(nrm, rb.partials + M.block_offset + blockIdx.x);
+        block_reduce_store(nrm, rb.partials + M.block_offset + tile);
         norm_epilogue(rb, M.total_blocks, st);
     }
 }
@@ -767,7 +787,11 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
 // fine-grid eta*, no stretching and no ell^-2.  Used twice per solve, so a
 // plain one-thread-per-node gather is enough.
 template <typename R, typename TI, typename TO>
-__global__ void __launch_bounds__(256) k_qapply(LevelArgs<R> L, const TI *__restrict__ x, TO *__restrict__ y) {
+__global__ void __launch_bounds__(256) k_qapply(LevelArgs<R> L, const TI *__restrict__ x, TO *__restrict__ y,
+                                               Batch bt) {
+    if (slot_off(bt, blockIdx.y)) return;
+    x = slot_ptr(x, (long long)(L.nz + 1) * L.sy, blockIdx.y);
+    y = slot_ptr(y, (long long)(L.nz + 1) * L.sy, blockIdx.y);
     extern __shared__ unsigned char smem_raw[];
     R *btab = reinterpret_cast<R *>(smem_raw);
     for (int i = threadIdx.x; i < L.K * 12; i += blockDim.x) btab[i] = L.btab[i];
@@ -832,7 +856,10 @@ __global__ void __launch_bounds__(256) k_diag(LevelArgs<R> L, const T *__restric
 // one Jacobi sweep from zero: y = omega D^-1 g (eq. jacobi-map with n_J = 1)
 template <typename R, typename T>
 __global__ void __launch_bounds__(256) k_jac1(const R *__restrict__ dinv, const T *__restrict__ g, T *__restrict__ y,
-                                              long long nn, R omegaJ) {
+                                              long long nn, R omegaJ, Batch bt) {
+    if (slot_off(bt, blockIdx.y)) return;
+    g = slot_ptr(g, nn, blockIdx.y);
+    y = slot_ptr(y, nn, blockIdx.y);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
         const Z<R> r = zscale(omegaJ, zmul(Z<R>{dinv[2 * i], dinv[2 * i + 1]}, ld<R>(g, i)));
         T o;
@@ -907,11 +934,12 @@ hipError_t launch_stencil_part(const LevelArgs<R> &L, const StencilCall &c, cons
     TY *y = (TY *)c.y;
     const R om = (R)c.omegaJ;
     const Scales sc = {c.sx, c.sg, c.sb, c.sy};
+    const Batch &bt = cur_batch();
 #define HELM_LAUNCH(MODE, SH, NRM)                                                                                  \
     do {                                                                                                            \
         if constexpr (mode_built<TX, TG, TY>(MODE, SH, NRM))                                                        \
-            hipLaunchKernelGGL((k_stencil<R, TX, TG, TY, MODE, SH, NRM, PART>), dim3(blocks), blk, shm, s, L, x, g,  \
-                               base, y, om, M, rb, c.st, sc);                                                       \
+            hipLaunchKernelGGL((k_stencil<R, TX, TG, TY, MODE, SH, NRM, PART>), dim3(blocks * bt.n), blk, shm, s, L, \
+                               x, g, base, y, om, M, rb, c.st, sc, bt);                                             \
         else                                                                                                        \
             return hipErrorInvalidValue;                                                                            \
     } while (0)

@@ -51,9 +51,15 @@ __global__ void __launch_bounds__(256) k_restrict(Geom F, Geom C, const T *__res
 // are written as zero.
 template <typename T, typename TO>
 __global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__restrict__ w, TO *__restrict__ c,
-                                                   Scale so) {
-    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zc = blockIdx.z;
+                                                   Scale so, Batch bt) {
+    // batched slots follow each other along z: slot sl covers planes sl (nc + 1) ..
+    const int sl = blockIdx.z / (C.n[2] + 1);
+    if (slot_off(bt, sl)) return;
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Zc = blockIdx.z % (C.n[2] + 1);
     if (X > C.n[0] || Y > C.n[1]) return;
+    w = slot_ptr(w, (long long)(C.n[2] + 1) * (F.n[1] + 1) * (C.n[0] + 1), sl);
+    c = slot_ptr(c, C.nn, sl);
+    so = slot_scale(so, sl);
     const real_of<T> ms = store_mul<real_of<T>, TO>(so);
     real_of<T> sr = 0, si = 0;
     if (X >= 1 && X <= C.n[0] - 1 && Y >= 1 && Y <= C.n[1] - 1 && Zc >= 1 && Zc <= C.n[2] - 1) {
@@ -76,10 +82,16 @@ __global__ void __launch_bounds__(256) k_restrict_y(Geom F, Geom C, const T *__r
 // a cell are adjacent in memory.
 template <typename T, typename TF>
 __global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__restrict__ c, TF *__restrict__ f,
-                                                    Scale sc, Scale sf) {
+                                                    Scale sc, Scale sf, Batch bt) {
     using R = std::conditional_t<is_half<TF>(), float, real_of<TF>>;   // FP16-stored vectors add in FP32
-    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Z = blockIdx.z;
+    const int sl = blockIdx.z / C.n[2];   // batched slots follow each other along z
+    if (slot_off(bt, sl)) return;
+    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Z = blockIdx.z % C.n[2];
     if (X >= C.n[0] || Y >= C.n[1]) return;
+    c = slot_ptr(c, C.nn, sl);
+    f = slot_ptr(f, F.nn, sl);
+    sc = slot_scale(sc, sl);
+    sf = slot_scale(sf, sl);
     // c16 operands: coarse values to true units, fine values through the fine scale
     const R mc = load_mul<R, T>(sc), mfl = load_mul<R, TF>(sf), mfs = store_mul<R, TF>(sf);
     // coarse corner values, zero outside the coarse interior
@@ -136,12 +148,13 @@ __global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__
 }  // namespace
 
 namespace {
-dim3 node_grid(const Geom &g) {
-    return dim3((unsigned)((g.n[0] + kTX) / kTX), (unsigned)((g.n[1] + kTY) / kTY), (unsigned)(g.n[2] + 1));
+// one thread per node of g (z planes repeated for each batched slot)
+dim3 node_grid(const Geom &g, int slots = 1) {
+    return dim3((unsigned)((g.n[0] + kTX) / kTX), (unsigned)((g.n[1] + kTY) / kTY), (unsigned)(g.n[2] + 1) * slots);
 }
-// one thread per cell of g: n[0] x n[1] x n[2]
-dim3 cell_grid(const Geom &g) {
-    return dim3((unsigned)((g.n[0] + kTX - 1) / kTX), (unsigned)((g.n[1] + kTY - 1) / kTY), (unsigned)g.n[2]);
+// one thread per cell of g: n[0] x n[1] x n[2] (z repeated for each batched slot)
+dim3 cell_grid(const Geom &g, int slots = 1) {
+    return dim3((unsigned)((g.n[0] + kTX - 1) / kTX), (unsigned)((g.n[1] + kTY - 1) / kTY), (unsigned)g.n[2] * slots);
 }
 }  // namespace
 
@@ -154,7 +167,8 @@ hipError_t launch_restrict(const Geom &fine, const Geom &coarse, const T *f, T *
 template <typename T, typename TO>
 hipError_t launch_restrict_y(const Geom &fine, const Geom &coarse, const T *w, TO *c, hipStream_t s, Scale so) {
     if (is_half<TO>() && !so.qs) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_restrict_y<T, TO>), node_grid(coarse), dim3(kTX, kTY), 0, s, fine, coarse, w, c, so);
+    const Batch &bt = cur_batch();
+    hipLaunchKernelGGL((k_restrict_y<T, TO>), node_grid(coarse, bt.n), dim3(kTX, kTY), 0, s, fine, coarse, w, c, so, bt);
     return hipGetLastError();
 }
 
@@ -164,7 +178,9 @@ hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, 
     if (fine.n[0] != 2 * coarse.n[0] || fine.n[1] != 2 * coarse.n[1] || fine.n[2] != 2 * coarse.n[2])
         return hipErrorInvalidValue;
     if ((is_half<T>() && !sc.qs) || (is_half<TF>() && !sf.qs)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_prolong_add<T, TF>), cell_grid(coarse), dim3(kTX, kTY), 0, s, coarse, fine, c, f, sc, sf);
+    const Batch &bt = cur_batch();
+    hipLaunchKernelGGL((k_prolong_add<T, TF>), cell_grid(coarse, bt.n), dim3(kTX, kTY), 0, s, coarse, fine, c, f, sc, sf,
+                       bt);
     return hipGetLastError();
 }
 

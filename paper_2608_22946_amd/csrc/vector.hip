@@ -16,6 +16,11 @@ namespace helm {
 constexpr int kSlots = kRedSlots;
 
 namespace {
+thread_local Batch g_batch;
+}
+Batch &cur_batch() { return g_batch; }
+
+namespace {
 
 template <typename T>
 using real_of = decltype(T{}.re);
@@ -200,7 +205,15 @@ struct Ptrs {
 // sums conj(V_j) w (j < NV) and optionally ||w||^2
 template <typename T, int NV, bool NORM, int EPI>
 __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restrict__ w, long long n, KState *st,
-                                             double *out, RedBuf rb) {
+                                             double *out, RedBuf rb, Batch bt) {
+    const int sl = blockIdx.y;
+    if (slot_off(bt, sl)) return;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) P.v[j] = slot_ptr(P.v[j], n, sl);
+    w = slot_ptr(w, n, sl);
+    st = slot_ptr(st, 1, sl);
+    out = slot_ptr(out, 2 * kSlots, sl);
+    rb = slot_rb(rb, bt, sl);
     constexpr int NS0 = NV + (NORM ? 1 : 0);
     constexpr int NS = NS0 > 0 ? NS0 : 1;
     D2 acc[NS];
@@ -265,8 +278,15 @@ __global__ void __launch_bounds__(1024) k_dots(Ptrs<T, NV> P, const T *__restric
 // cycle needs only the Hessenberg column and h_{k+1,k}, not the next basis vector.
 template <typename T, int NV, bool STORE>
 __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict__ w, long long n, KState *st,
-                                                  RedBuf rb) {
-    if (!st->reorth) return;   // the first pass was enough (the whole grid returns; no ticket is taken)
+                                                  RedBuf rb, Batch bt) {
+    const int sl = blockIdx.y;
+    if (slot_off(bt, sl)) return;
+    st = slot_ptr(st, 1, sl);
+    if (!st->reorth) return;   // the first pass was enough (the slot's blocks return; no ticket is taken)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) P.v[j] = slot_ptr(P.v[j], n, sl);
+    w = slot_ptr(w, n, sl);
+    rb = slot_rb(rb, bt, sl);
     __shared__ double hs[NV][2];
     if (threadIdx.x < NV) {   // coefficients of the stored vectors (V_0 is stored unnormalised)
         const double f = threadIdx.x == 0 ? st->vs0 : 1.0;
@@ -320,7 +340,14 @@ __global__ void __launch_bounds__(1024) k_axpy_dots(Ptrs<T, NV> P, T *__restrict
 
 // w <- (w - sum_j h2_j V_j) * scale
 template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_axpy_scale(Ptrs<T, NV> P, T *__restrict__ w, long long n, const KState *st) {
+__global__ void __launch_bounds__(256) k_axpy_scale(Ptrs<T, NV> P, T *__restrict__ w, long long n, const KState *st,
+                                                   Batch bt) {
+    const int sl = blockIdx.y;
+    if (slot_off(bt, sl)) return;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) P.v[j] = slot_ptr(P.v[j], n, sl);
+    w = slot_ptr(w, n, sl);
+    st = slot_ptr(st, 1, sl);
     __shared__ double hs[NV + 1][2];
     if (threadIdx.x < NV) {   // coefficients of the stored vectors (V_0 is stored unnormalised)
         const double f = threadIdx.x == 0 ? st->vs0 : 1.0;
@@ -352,8 +379,9 @@ __global__ void __launch_bounds__(256) k_axpy_scale(Ptrs<T, NV> P, T *__restrict
 
 // y = R^{-1} g: back substitution of the rotated Hessenberg over its kk columns
 // (guarded zero pivots), y_j = 0 beyond; one thread.
-__global__ void __launch_bounds__(64) k_backsolve(KState *st, int nv) {
-    if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(64) k_backsolve(KState *st, int nv, Batch bt) {
+    if (threadIdx.x != 0 || slot_off(bt, blockIdx.y)) return;
+    st = slot_ptr(st, 1, blockIdx.y);
     const int kk = st->kk < nv ? st->kk : nv;
     for (int j = kk; j < kMMax; ++j) st->y[j][0] = st->y[j][1] = 0.0;
     for (int i = kk - 1; i >= 0; --i) {
@@ -378,7 +406,13 @@ __global__ void __launch_bounds__(64) k_backsolve(KState *st, int nv) {
 // s-step Gram solve)
 template <typename TX, typename TZ, int NV>
 __global__ void __launch_bounds__(256) k_combine(TX *__restrict__ x, Ptrs<TZ, NV> Zp, long long n, const KState *st,
-                                                int overwrite, float zf) {
+                                                int overwrite, float zf, Batch bt) {
+    const int sl = blockIdx.y;
+    if (slot_off(bt, sl)) return;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) Zp.v[j] = slot_ptr(Zp.v[j], n, sl);
+    x = slot_ptr(x, n, sl);
+    st = slot_ptr(st, 1, sl);
     using RA = std::conditional_t<is_half<TX>(), float, real_of<TX>>;   // FP16-stored x adds in FP32
     __shared__ double ys[NV][2];
     if (threadIdx.x < NV) {
@@ -418,7 +452,13 @@ __global__ void __launch_bounds__(256) k_combine(TX *__restrict__ x, Ptrs<TZ, NV
 
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) k_convert_scaled(const TI *__restrict__ x, TO *__restrict__ y, long long n,
-                                                       Scale si, Scale so) {
+                                                       Scale si, Scale so, Batch bt) {
+    const int sl = blockIdx.y;
+    if (slot_off(bt, sl)) return;
+    x = slot_ptr(x, n, sl);
+    y = slot_ptr(y, n, sl);
+    si = slot_scale(si, sl);
+    so = slot_scale(so, sl);
     using RA = std::conditional_t<is_half<TO>(), float, real_of<TO>>;
     const long long i = elem_index();
     if (i >= n) return;
@@ -431,7 +471,13 @@ __global__ void __launch_bounds__(256) k_convert_scaled(const TI *__restrict__ x
 // the least-squares coefficients y of min ||P_0 - [P_1..P_{NP-1}] y|| from the
 // normal equations by Cholesky (truncated at a vanishing pivot).
 template <typename T, int NP>
-__global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KState *st, RedBuf rb) {
+__global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KState *st, RedBuf rb, Batch bt) {
+    const int sl = blockIdx.y;
+    if (slot_off(bt, sl)) return;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) P.v[a] = slot_ptr(P.v[a], n, sl);
+    st = slot_ptr(st, 1, sl);
+    rb = slot_rb(rb, bt, sl);
     constexpr int NS = NP * (NP + 1) / 2;
     D2 acc[NS];
 #pragma unroll
@@ -513,7 +559,9 @@ __global__ void __launch_bounds__(1024) k_gram(Ptrs<T, NP> P, long long n, KStat
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_fill_zero(T *x, long long n) {
+__global__ void __launch_bounds__(256) k_fill_zero(T *x, long long n, Batch bt) {
+    if (slot_off(bt, blockIdx.y)) return;
+    x = slot_ptr(x, n, blockIdx.y);
     const long long i = elem_index();
     if (i >= n) return;
     T z;
@@ -523,7 +571,10 @@ __global__ void __launch_bounds__(256) k_fill_zero(T *x, long long n) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_add(const T *__restrict__ x, T *__restrict__ y, long long n) {
+__global__ void __launch_bounds__(256) k_add(const T *__restrict__ x, T *__restrict__ y, long long n, Batch bt) {
+    if (slot_off(bt, blockIdx.y)) return;
+    x = slot_ptr(x, n, blockIdx.y);
+    y = slot_ptr(y, n, blockIdx.y);
     const long long i = elem_index();
     if (i >= n) return;
     T v = y[i];
@@ -534,7 +585,10 @@ __global__ void __launch_bounds__(256) k_add(const T *__restrict__ x, T *__restr
 }
 
 template <typename TI, typename TO>
-__global__ void __launch_bounds__(256) k_convert(const TI *__restrict__ x, TO *__restrict__ y, long long n) {
+__global__ void __launch_bounds__(256) k_convert(const TI *__restrict__ x, TO *__restrict__ y, long long n, Batch bt) {
+    if (slot_off(bt, blockIdx.y)) return;
+    x = slot_ptr(x, n, blockIdx.y);
+    y = slot_ptr(y, n, blockIdx.y);
     const long long i = elem_index();
     if (i >= n) return;
     TO o;
@@ -652,23 +706,23 @@ hipError_t launch_dots(const T *const *V, int nv, const T *w, bool norm, long lo
     case NV:                                                                                                        \
         if (norm) {                                                                                                 \
             if (epi == EPI_STORE)                                                                                   \
-                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_STORE>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, \
-                                   st, out, rb);                                                                    \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_STORE>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, \
+                                   st, out, rb, cur_batch());                                                                    \
             else if (epi == EPI_NORM_INIT)                                                                          \
-                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_NORM_INIT>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), \
-                                   w, n, st, out, rb);                                                              \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_NORM_INIT>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s, pack<T, NV>(V), \
+                                   w, n, st, out, rb, cur_batch());                                                              \
             else if (epi == EPI_ARNOLDI_SEL && NV > 0)                                                              \
-                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_ARNOLDI_SEL>), dim3(nb), dim3(kRedThreads), 0, s,         \
-                                   pack<T, NV>(V), w, n, st, out, rb);                                              \
+                hipLaunchKernelGGL((k_dots<T, NV, true, EPI_ARNOLDI_SEL>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s,         \
+                                   pack<T, NV>(V), w, n, st, out, rb, cur_batch());                                              \
             else                                                                                                    \
                 return hipErrorInvalidValue;                                                                        \
         } else {                                                                                                    \
             if (epi == EPI_STORE)                                                                                   \
-                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_STORE>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, \
-                                   n, st, out, rb);                                                                 \
+                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_STORE>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, \
+                                   n, st, out, rb, cur_batch());                                                                 \
             else if (epi == EPI_ARNOLDI1)                                                                           \
-                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_ARNOLDI1>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), \
-                                   w, n, st, out, rb);                                                              \
+                hipLaunchKernelGGL((k_dots<T, NV, false, EPI_ARNOLDI1>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s, pack<T, NV>(V), \
+                                   w, n, st, out, rb, cur_batch());                                                              \
             else                                                                                                    \
                 return hipErrorInvalidValue;                                                                        \
         }                                                                                                           \
@@ -690,11 +744,11 @@ hipError_t launch_axpy_dots(const T *const *V, int nv, T *w, long long n, KState
 #define HELM_AD(NV)                                                                                                \
     case NV:                                                                                                       \
         if (store)                                                                                                 \
-            hipLaunchKernelGGL((k_axpy_dots<T, NV, true>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, \
-                               st, rb);                                                                            \
+            hipLaunchKernelGGL((k_axpy_dots<T, NV, true>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s, pack<T, NV>(V), w, n, \
+                               st, rb, cur_batch());                                                               \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_axpy_dots<T, NV, false>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NV>(V), w,  \
-                               n, st, rb);                                                                         \
+            hipLaunchKernelGGL((k_axpy_dots<T, NV, false>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s, pack<T, NV>(V), w,  \
+                               n, st, rb, cur_batch());                                                            \
         break;
     switch (nv) {
         HELM_AD(1) HELM_AD(2) HELM_AD(3) HELM_AD(4) HELM_AD(5) HELM_AD(6) HELM_AD(7) HELM_AD(8) HELM_AD(9)
@@ -710,7 +764,7 @@ template <typename T>
 hipError_t launch_axpy_scale(const T *const *V, int nv, T *w, long long n, KState *st, hipStream_t s) {
     const unsigned nb = stream_blocks(n);
 #define HELM_AS(NV) \
-    case NV: hipLaunchKernelGGL((k_axpy_scale<T, NV>), dim3(nb), dim3(256), 0, s, pack<T, NV>(V), w, n, st); break;
+    case NV: hipLaunchKernelGGL((k_axpy_scale<T, NV>), dim3(nb, cur_batch().n), dim3(256), 0, s, pack<T, NV>(V), w, n, st, cur_batch()); break;
     switch (nv) {
         HELM_AS(1) HELM_AS(2) HELM_AS(3) HELM_AS(4) HELM_AS(5) HELM_AS(6) HELM_AS(7) HELM_AS(8) HELM_AS(9)
         HELM_AS(10) HELM_AS(11) HELM_AS(12)
@@ -726,15 +780,15 @@ hipError_t launch_combine(TX *x, const TZ *const *Z, int nz, long long n, KState
                           bool overwrite, hipStream_t s, float zf) {
     if (nz < 1 || nz > kMMax) return hipErrorInvalidValue;
     if (from_backsolve) {
-        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, st, nz);
+        hipLaunchKernelGGL(k_backsolve, dim3(1, cur_batch().n), dim3(64), 0, s, st, nz, cur_batch());
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     const unsigned nb = stream_blocks(n);
 #define HELM_CB(NV)                                                                                            \
     case NV:                                                                                                   \
-        hipLaunchKernelGGL((k_combine<TX, TZ, NV>), dim3(nb), dim3(256), 0, s, x, pack<TZ, NV>(Z), n, st,       \
-                           (int)overwrite, zf);                                                                \
+        hipLaunchKernelGGL((k_combine<TX, TZ, NV>), dim3(nb, cur_batch().n), dim3(256), 0, s, x, pack<TZ, NV>(Z), n, st,       \
+                           (int)overwrite, zf, cur_batch());                                                                \
         break;
     switch (nz) {
         HELM_CB(1) HELM_CB(2) HELM_CB(3) HELM_CB(4) HELM_CB(5) HELM_CB(6) HELM_CB(7) HELM_CB(8) HELM_CB(9)
@@ -750,7 +804,7 @@ template <typename T>
 hipError_t launch_gram(const T *const *P, int np, long long n, KState *st, const RedBuf &rb, hipStream_t s) {
     const int nb = red_blocks(n);
 #define HELM_GR(NP) \
-    case NP: hipLaunchKernelGGL((k_gram<T, NP>), dim3(nb), dim3(kRedThreads), 0, s, pack<T, NP>(P), n, st, rb); break;
+    case NP: hipLaunchKernelGGL((k_gram<T, NP>), dim3(nb, cur_batch().n), dim3(kRedThreads), 0, s, pack<T, NP>(P), n, st, rb, cur_batch()); break;
     switch (np) {
         HELM_GR(2) HELM_GR(3) HELM_GR(4) HELM_GR(5) HELM_GR(6) HELM_GR(7) HELM_GR(8) HELM_GR(9)
     default:
@@ -762,19 +816,19 @@ hipError_t launch_gram(const T *const *P, int np, long long n, KState *st, const
 
 template <typename T>
 hipError_t launch_fill_zero(T *x, long long n, hipStream_t s) {
-    hipLaunchKernelGGL((k_fill_zero<T>), dim3(stream_blocks(n)), dim3(256), 0, s, x, n);
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(stream_blocks(n), cur_batch().n), dim3(256), 0, s, x, n, cur_batch());
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_add(const T *x, T *y, long long n, hipStream_t s) {
-    hipLaunchKernelGGL((k_add<T>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n);
+    hipLaunchKernelGGL((k_add<T>), dim3(stream_blocks(n), cur_batch().n), dim3(256), 0, s, x, y, n, cur_batch());
     return hipGetLastError();
 }
 
 template <typename TI, typename TO>
 hipError_t launch_convert(const TI *x, TO *y, long long n, hipStream_t s) {
-    hipLaunchKernelGGL((k_convert<TI, TO>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n);
+    hipLaunchKernelGGL((k_convert<TI, TO>), dim3(stream_blocks(n), cur_batch().n), dim3(256), 0, s, x, y, n, cur_batch());
     return hipGetLastError();
 }
 
@@ -822,7 +876,8 @@ template hipError_t launch_gram<c16>(const c16 *const *, int, long long, KState 
 template <typename TI, typename TO>
 hipError_t launch_convert_scaled(const TI *x, TO *y, long long n, Scale si, Scale so, hipStream_t s) {
     if ((is_half<TI>() && !si.qs) || (is_half<TO>() && !so.qs)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_convert_scaled<TI, TO>), dim3(stream_blocks(n)), dim3(256), 0, s, x, y, n, si, so);
+    hipLaunchKernelGGL((k_convert_scaled<TI, TO>), dim3(stream_blocks(n), cur_batch().n), dim3(256), 0, s, x, y, n, si,
+                       so, cur_batch());
     return hipGetLastError();
 }
 template hipError_t launch_convert_scaled<c32, c16>(const c32 *, c16 *, long long, Scale, Scale, hipStream_t);

@@ -33,7 +33,8 @@ class HelmOptions(ctypes.Structure):
                 ("m_h", _c_int), ("c_2h", _c_int), ("m_2h", _c_int), ("m_4h", _c_int), ("m_out", _c_int),
                 ("max_outer", _c_int),
                 ("iofd_table", _c_void_p), ("iofd_K", _c_int), ("stream", _c_void_p),
-                ("tile_tz", _c_int), ("tile_split", _c_int), ("lanes", _c_int), ("pml_variant", _c_int)]
+                ("tile_tz", _c_int), ("tile_split", _c_int), ("lanes", _c_int), ("pml_variant", _c_int),
+                ("batch", _c_int)]
 
 
 EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_solve", "helm_solve_checkpoint",

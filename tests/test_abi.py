@@ -100,6 +100,16 @@ def test_workspace_grows_by_one_solver_copy_per_lane(L):
     assert _ws(L, (56, 56, 56), 4, _opts(lanes=0))[1] == sizes[0]
 
 
+def test_workspace_grows_linearly_with_batch(L):
+    """Each batched slot holds one more copy of the lane's vectors, states and partials."""
+    sizes = [_ws(L, (56, 56, 56), 4, _opts(batch=k))[1] for k in (1, 2, 3)]
+    # equal steps up to the 256-byte alignment of the workspace slices
+    assert sizes[1] > sizes[0] and abs((sizes[2] - sizes[1]) - (sizes[1] - sizes[0])) <= 256 * 64
+    assert _ws(L, (56, 56, 56), 4, _opts(batch=0))[1] == sizes[0]
+    # one slot's copy is at least the lane's fine-level vectors (outer 11, smoother 5, x, b, temporary)
+    assert sizes[1] - sizes[0] >= 65 ** 3 * (17 * 8 + 2 * 16)
+
+
 def test_good_tile_options_accepted(L):
     for tz in (0, 2, 4, 8, 16, 32, 64):
         for split in (-1, 0, 1):
@@ -110,7 +120,8 @@ def test_good_tile_options_accepted(L):
 @pytest.mark.parametrize("field,value", [("m_out", 0), ("m_2h", 13), ("m_4h", 9), ("nJ_h", 0), ("c_2h", 0),
                                          ("iofd_K", 0), ("omega_2h", -0.1), ("struct_size", 8), ("precision", 7),
                                          ("tile_tz", 3), ("tile_tz", 128), ("tile_split", 2), ("tile_split", -2),
-                                         ("lanes", 9), ("lanes", -1), ("pml_variant", 3), ("pml_variant", -1)])
+                                         ("lanes", 9), ("lanes", -1), ("pml_variant", 3), ("pml_variant", -1),
+                                         ("batch", 9), ("batch", -1)])
 def test_bad_options_rejected(L, field, value):
     rc, _ = _ws(L, (24, 24, 24), 4, _opts(**{field: value}))
     assert rc == -1
