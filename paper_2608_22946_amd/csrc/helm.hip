@@ -63,6 +63,7 @@ struct helm_hierarchy {
     int nphys[3];
     int n_pml;
     double h, omega;
+    double cmin, cmax;   // velocity range (the level velocities lie inside it)
     hipStream_t s;
     Geom geom[3];
     LevelArgs<float> Lf[3];
@@ -357,6 +358,33 @@ void fill_level_args(helm_hierarchy *H, int l, LevelArgs<R> &L, const R *wx, con
     L.s = fp32 ? H->svel[l] : nullptr;
     L.ctab = fp32 ? reinterpret_cast<const R *>(H->ctab_f) : nullptr;
     L.kap_s = (R)(2.0 * M_PI * 0.4 / H->opt.iofd_K);
+    // table window: the interval of a node is monotone in its velocity, so the velocity
+    // range [cmin, cmax] bounds it; the same formulas as the kernels (locate / locate_s,
+    // shell_at_s), widened by one interval each side against rounding
+    const int K = H->opt.iofd_K;
+    auto clampi = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
+    int ka, kz, ca = 0, cz = K;
+    if (fp32) {
+        const double factor = H->omega * g.ell * K / (0.4 * 2.0 * M_PI);
+        const float slo = (float)(factor / H->cmax), shi = (float)(factor / H->cmin);
+        auto kof = [&](float sv) { return clampi((int)std::min(sv, (float)K), 0, K - 1); };
+        ka = kof(slo);
+        kz = kof(shi);
+        ca = clampi((int)slo, 0, K);
+        cz = clampi((int)shi, 0, K);
+    } else {
+        auto kof = [&](double c) {
+            double eta = (H->omega * g.ell * (1.0 / c)) * 0.15915494309189533577;
+            eta = eta < 0.4 ? eta : 0.4;
+            return clampi((int)(eta * (K / 0.4)), 0, K - 1);
+        };
+        ka = kof(H->cmax);
+        kz = kof(H->cmin);
+    }
+    L.kb = clampi(ka - 1, 0, K - 1);
+    L.nk = clampi(kz + 1, 0, K - 1) - L.kb + 1;
+    L.cb = clampi(ca - 1, 0, K);
+    L.nck = clampi(cz + 1, 0, K) - L.cb + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1172,6 +1200,8 @@ helm_status helm_setup(const float *velocity, int nx, int ny, int nz, double h, 
         return bail(HELM_EHIP, std::string("velocity check: ") + hipGetErrorString(e));
     if (H->lane[0].host_scratch[2] != 0.0 || !(H->lane[0].host_scratch[0] > 0.0))
         return bail(HELM_EINVAL, "velocity must be finite and positive everywhere");
+    H->cmin = H->lane[0].host_scratch[0];
+    H->cmax = H->lane[0].host_scratch[1];
 
     const double Lpml = n_pml * h;
     std::vector<double> w;

@@ -127,6 +127,10 @@ struct LevelArgs {
     const float *s;
     const R *ctab;       // [K + 1][4][6] monomial coefficients in t
     R kap_s;             // kappa per unit of s: 0.4 * 2 pi / K
+    // table intervals the stencils stage in LDS: the alpha pieces kb .. kb + nk - 1 and the
+    // shell quintics cb .. cb + nck - 1, every interval a node of this level can reach
+    // (from the velocity range, one interval of margin each side)
+    int kb, nk, cb, nck;
 };
 
 // ---------------------------------------------------------------------------

@@ -25,9 +25,9 @@ hipError_t launch_diag(const LevelArgs<R> &L, int shifted, const T *x, T *y, hip
     const long long nn = (long long)(L.nz + 1) * L.sy;
     int blocks = (int)std::min<long long>((nn + 255) / 256, 65536);
     if (shifted)
-        hipLaunchKernelGGL((k_diag<R, T, true>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, x, y);
+        hipLaunchKernelGGL((k_diag<R, T, true>), dim3(blocks), dim3(256), sizeof(R) * L.nk * 20, s, L, x, y);
     else
-        hipLaunchKernelGGL((k_diag<R, T, false>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, x, y);
+        hipLaunchKernelGGL((k_diag<R, T, false>), dim3(blocks), dim3(256), sizeof(R) * L.nk * 20, s, L, x, y);
     return hipGetLastError();
 }
 
@@ -47,9 +47,9 @@ hipError_t launch_dinv(const LevelArgs<R> &L, int shifted, R *out, hipStream_t s
     const long long nn = (long long)(L.nz + 1) * L.sy;
     int blocks = (int)std::min<long long>((nn + 255) / 256, 65536);
     if (shifted)
-        hipLaunchKernelGGL((k_dinv<R, true>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, out);
+        hipLaunchKernelGGL((k_dinv<R, true>), dim3(blocks), dim3(256), sizeof(R) * L.nk * 20, s, L, out);
     else
-        hipLaunchKernelGGL((k_dinv<R, false>), dim3(blocks), dim3(256), sizeof(R) * L.K * 20, s, L, out);
+        hipLaunchKernelGGL((k_dinv<R, false>), dim3(blocks), dim3(256), sizeof(R) * L.nk * 20, s, L, out);
     return hipGetLastError();
 }
 template hipError_t launch_dinv<float>(const LevelArgs<float> &, int, float *, hipStream_t);

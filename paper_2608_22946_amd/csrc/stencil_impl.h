@@ -155,7 +155,9 @@ __device__ __forceinline__ Coef<R> coef_at(const LevelArgs<R> &L, const R *stab,
         locate_s(L, v, kappa, k, t);
     else
         locate(L, v, kappa, k, t);
-    const R *p = stab + k * 20;
+    // stab holds the intervals kb .. kb + nk - 1 (the level's window)
+    k = k < L.kb ? L.kb : (k > L.kb + L.nk - 1 ? L.kb + L.nk - 1 : k);
+    const R *p = stab + (k - L.kb) * 20;
     Coef<R> o;
     o.a1 = horner(p + 0, t);
     o.a2 = horner(p + 4, t);
@@ -174,7 +176,9 @@ __device__ __forceinline__ void shell_at_s(const LevelArgs<R> &L, const R *ctab,
     int k = (int)s;
     k = k < L.K ? k : L.K;
     const R t = (R)s - (R)k;
-    const R *p = ctab + k * 24;
+    // ctab holds the intervals cb .. cb + nck - 1 (the level's window)
+    const int kw = k < L.cb ? L.cb : (k > L.cb + L.nck - 1 ? L.cb + L.nck - 1 : k);
+    const R *p = ctab + (kw - L.cb) * 24;
     c0 = horner5(p, t);
     c1 = horner5(p + 6, t);
     c2 = horner5(p + 12, t);
@@ -543,7 +547,7 @@ __device__ __forceinline__ void march(const LevelArgs<R> &L, const R *stab, cons
             const bool zint = (z >= L.loz && z <= L.hiz);
             const R *wzp = L.wz + 6 * z;
             const Z<R> wz[3] = {{wzp[0], wzp[1]}, {wzp[2], wzp[3]}, {wzp[4], wzp[5]}};
-            const Z<R> Hv = row_value<R, XI && YI, SHIFT>(L, stab, stab + 20 * L.K, m, o, p, zint, wz);
+            const Z<R> Hv = row_value<R, XI && YI, SHIFT>(L, stab, stab + 20 * L.nk, m, o, p, zint, wz);
             if (MODE == M_APPLY) {
                 res = Hv;
             } else if (MODE == M_RESID || RESTRICT) {
@@ -671,9 +675,10 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
     extern __shared__ unsigned char smem_raw[];
     R *stab = reinterpret_cast<R *>(smem_raw);   // alpha pieces, then (FP32) the shell quintics
     const int tid = threadIdx.x + 64 * threadIdx.y;
-    for (int i = tid; i < L.K * 20; i += 256) stab[i] = L.atab[i];
+    // the level's window of table intervals only (at 4h almost every node is in the clamped one)
+    for (int i = tid; i < L.nk * 20; i += 256) stab[i] = L.atab[L.kb * 20 + i];
     if (scaled_coordinate<R>())
-        for (int i = tid; i < (L.K + 1) * 24; i += 256) stab[L.K * 20 + i] = L.ctab[i];
+        for (int i = tid; i < L.nck * 24; i += 256) stab[L.nk * 20 + i] = L.ctab[L.cb * 24 + i];
     __syncthreads();
 
     const int ntx = M.ntx, nty = M.nty;
@@ -832,7 +837,7 @@ template <typename R, typename T, bool SHIFT>
 __global__ void __launch_bounds__(256) k_diag(LevelArgs<R> L, const T *__restrict__ x, T *__restrict__ y) {
     extern __shared__ unsigned char smem_raw[];
     R *stab = reinterpret_cast<R *>(smem_raw);
-    for (int i = threadIdx.x; i < L.K * 20; i += blockDim.x) stab[i] = L.atab[i];
+    for (int i = threadIdx.x; i < L.nk * 20; i += blockDim.x) stab[i] = L.atab[L.kb * 20 + i];
     __syncthreads();
     const long long nn = (long long)(L.nz + 1) * L.sy;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
@@ -876,7 +881,7 @@ template <typename R, bool SHIFT>
 __global__ void __launch_bounds__(256) k_dinv(LevelArgs<R> L, R *__restrict__ out) {
     extern __shared__ unsigned char smem_raw[];
     R *stab = reinterpret_cast<R *>(smem_raw);
-    for (int i = threadIdx.x; i < L.K * 20; i += blockDim.x) stab[i] = L.atab[i];
+    for (int i = threadIdx.x; i < L.nk * 20; i += blockDim.x) stab[i] = L.atab[L.kb * 20 + i];
     __syncthreads();
     const long long nn = (long long)(L.nz + 1) * L.sy;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
@@ -927,7 +932,7 @@ template <typename R, typename TX, typename TG, typename TY, int PART>
 hipError_t launch_stencil_part(const LevelArgs<R> &L, const StencilCall &c, const RedBuf &rb, const TileMap &M,
                                int blocks, hipStream_t s) {
     const dim3 blk(64, kWavesY);
-    const size_t shm = sizeof(R) * (L.K * 20 + (scaled_coordinate<R>() ? (L.K + 1) * 24 : 0));
+    const size_t shm = sizeof(R) * (L.nk * 20 + (scaled_coordinate<R>() ? L.nck * 24 : 0));
     const TX *x = (const TX *)c.x;
     const TG *g = (const TG *)c.g;
     const TY *base = (const TY *)c.base;
