@@ -193,6 +193,39 @@ __device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const TX *__r
     }
 }
 
+// Blocks whose staged rows are all free of stretching (eq. iofd-shell-form): row i has the
+// coefficient C_m(i) (minus i sigma kappa_i^2 M_m(i) when shifted) on its shell-m neighbours, so
+// (op^T x)_j = ell^-2 sum_m sum_{i in shell m of j} C_m(i) x_i.  Each staged node then holds
+// u_m = C_m(i) x_i (m = 0..3) and the outputs are plain shell sums of the u_m, with no
+// per-neighbour coefficient arithmetic.
+template <typename R, typename TX, bool SHIFT>
+__device__ __forceinline__ void stage_plane_shell(const LevelArgs<R> &L, const TX *__restrict__ x, int X0, int Y0,
+                                                  int z, R (*S)[kHN]) {
+    const int tid = threadIdx.y * kTX + threadIdx.x;
+    for (int e = tid; e < kHN; e += kTX * kTY) {
+        const int c = e % kHX, r = e / kHX;
+        const int xi = X0 - 1 + c, yi = Y0 - 1 + r;
+        const long long i = (long long)z * L.sy + (long long)yi * L.sx + xi;   // an interior node
+        const Zc<R> xv = load<R>(x, i);
+        const Loc<R> q = locate_at(L, L.c[i]);
+        const R *p = L.atab + q.k * 20;
+        R a[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) a[f] = hval(p + 4 * f, q.t);
+        const R k2 = q.kappa * q.kappa;
+        const R qq = (R)1 - a[3] - a[4];
+        const R M[4] = {a[0], a[1] * (R)(1.0 / 6), a[2] * (R)(1.0 / 12), ((R)1 - a[0] - a[1] - a[2]) * (R)0.125};
+        const R C[4] = {(R)6 * a[3] - k2 * M[0], (a[4] - a[3]) - k2 * M[1], (R)0.5 * (qq - a[4]) - k2 * M[2],
+                        (R)-0.75 * qq - k2 * M[3]};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const R ci = SHIFT ? -L.sigma * k2 * M[m] : (R)0;
+            S[2 * m][e] = C[m] * xv.r - ci * xv.i;
+            S[2 * m + 1][e] = C[m] * xv.i + ci * xv.r;
+        }
+    }
+}
+
 template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RESID>
 __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
                                                 TY *__restrict__ y) {
@@ -209,9 +242,31 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
         Wx[d + 1] = inxy ? axis_w(L.wx, X + d, -d) : Zc<R>{0, 0};
         Wy[d + 1] = inxy ? axis_w(L.wy, Y + d, -d) : Zc<R>{0, 0};
     }
+    // every row the block stages (x X0-1..X0+64, y Y0-1..Y0+4, planes Zb-1..Ze) free of stretching
+    const bool shell = X0 - 1 >= L.lox && X0 + kTX <= L.hix && Y0 - 1 >= L.loy && Y0 + kTY <= L.hiy &&
+                       Zb - 1 >= L.loz && Ze <= L.hiz;
     // acc[0], acc[1], acc[2]: running sums of the outputs in planes p - 1, p, p + 1
     Zc<R> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
     for (int p = Zb - 1; p <= Ze; ++p) {
+        if (shell) {
+            stage_plane_shell<R, TX, SHIFT>(L, x, X0, Y0, p, S);
+            __syncthreads();
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int e = (threadIdx.y + 1 + dy) * kHX + threadIdx.x + 1 + dx;
+                    const int m = (dx != 0) + (dy != 0);   // shell of this neighbour in its own plane
+                    const R u0r = S[2 * m][e], u0i = S[2 * m + 1][e];           // same plane: shell m
+                    const R u1r = S[2 * m + 2][e], u1i = S[2 * m + 3][e];       // planes p -+ 1: shell m + 1
+                    acc[1].r += u0r;
+                    acc[1].i += u0i;
+                    acc[0].r += u1r;
+                    acc[0].i += u1i;
+                    acc[2].r += u1r;
+                    acc[2].i += u1i;
+                }
+        } else {
         stage_plane(L, x, X0, Y0, p, S);
         __syncthreads();
         if (inxy && p >= 1 && p <= L.nz - 1) {   // only interior planes hold rows
@@ -242,6 +297,7 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
                         a.i += cf.r * xi + cf.i * xr;
                     }
                 }
+        }
         }
         const int z = p - 1;   // all three neighbour planes of output plane p - 1 are in
         if (col && z >= Zb && z < Ze) {

@@ -570,6 +570,20 @@ def test_apply_transposed(pair, level, op):
     assert err <= pair.tol(1e-12, 1e-6), err
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("op", [5, 6])
+def test_apply_transposed_shell_blocks(precision, op):
+    """A^T / B^T on a grid wide enough that whole 64 x 4 x 16 blocks and their halos lie
+    outside the PML (the shell-sum path) next to blocks that touch it (the tensor path):
+    180 x 24 x 40 physical + 4 PML cells, GRF velocity, against the oracle's transposes."""
+    vel = grf_velocity(180, 24, 40, seed=18, corr_len=6.0)
+    p = Pair(vel, 4, precision)
+    x = p.rand(0, 240 + op)
+    err = rel(to_np(p.g.apply(0, op, p.dev(x))), p.o.apply_t(0, op - 5, x.astype(complex)))
+    print(f"\n{precision} op {op}: {err:.2e}")
+    assert err <= p.tol(1e-12, 1e-6), err
+
+
 @pytest.mark.parametrize("op", [8, 9])
 def test_apply_row_derivative(pair, op):
     """y_i = (d_i A_h x)_i and (d_i Q_h x)_i, m = 1/c^2, against the oracle."""
