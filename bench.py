@@ -330,8 +330,10 @@ def multi_rhs(configs=((1, 1), (4, 1), (1, 4), (1, 8), (2, 4), (2, 8)), seed=3):
     srcs = [(x, y, npml + 20) for y in xs for x in xs]
     f = torch.from_numpy(np.stack([point_source((N, N, N), s_, H, dtype=np.complex64) for s_ in srcs])).to(dev)
     base = None
-    for lanes, batch in configs:
-        Hh = helm.Hierarchy(torch.from_numpy(vel), H, omega, npml, precision="fp32", table=table, device=dev,
+    for cfg in configs:
+        lanes, batch = cfg[0], cfg[1]
+        prec = cfg[2] if len(cfg) > 2 else "fp32"
+        Hh = helm.Hierarchy(torch.from_numpy(vel), H, omega, npml, precision=prec, table=table, device=dev,
                             lanes=lanes, batch=batch)
         u = torch.empty_like(f)
         w = lanes * batch
@@ -345,7 +347,7 @@ def multi_rhs(configs=((1, 1), (4, 1), (1, 4), (1, 8), (2, 4), (2, 8)), seed=3):
         if base is None:
             base = per
         print(json.dumps({"metric": "time-to-rel.res 1e-6 per source, many sources", "value": round(per, 4),
-                          "unit": "s per source", "lanes": lanes, "batch": batch,
+                          "unit": "s per source", "lanes": lanes, "batch": batch, "precision": prec,
                           "speedup_vs_single_rhs": round(base / per, 3), "sources": len(srcs),
                           "total_s": round(dt, 3), "pc_calls_mean": float(np.mean(its)),
                           "pc_calls_max": int(np.max(its)), "max_relres": float(np.max(rel)),
@@ -656,7 +658,7 @@ def main():
     ap.add_argument("--multi-rhs", action="store_true",
                     help="run the 64-source 288^3 layered workload over (lanes, batch) settings instead")
     ap.add_argument("--multi-rhs-configs", default="",
-                    help="with --multi-rhs: comma-separated LANESxBATCH settings, e.g. 1x1,1x8")
+                    help="with --multi-rhs: comma-separated LANESxBATCH[:PRECISION] settings, e.g. 1x1,1x8,2x8:mixed")
     ap.add_argument("--grad", action="store_true",
                     help="time the adjoint misfit gradient on the benchmark workload instead")
     ap.add_argument("--green-pml", action="store_true",
@@ -678,7 +680,12 @@ def main():
         return
     if args.multi_rhs:
         if args.multi_rhs_configs:
-            multi_rhs(tuple(tuple(int(v) for v in c.split("x")) for c in args.multi_rhs_configs.split(",")))
+            cfgs = []
+            for c in args.multi_rhs_configs.split(","):   # LANESxBATCH, or LANESxBATCH:PRECISION
+                shape, _, prec = c.partition(":")
+                lanes, batch = (int(v) for v in shape.split("x"))
+                cfgs.append((lanes, batch) + ((prec,) if prec else ()))
+            multi_rhs(tuple(cfgs))
         else:
             multi_rhs()
         return
