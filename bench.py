@@ -139,7 +139,9 @@ def cpu_baseline(vel, omega, table, gpu_pc_calls):
     FP64 A_h apply at the full size on all threads and on one thread."""
     from oracle.oracle import Hierarchy as OracleHierarchy
     from workloads import random_complex
+    t0 = time.perf_counter()
     O = OracleHierarchy(vel, H, omega, N_PML, table)
+    t_setup = time.perf_counter() - t0
     N = N_PHYS + 2 * N_PML
     r = random_complex((N, N, N), 7)
     r /= np.linalg.norm(r)
@@ -160,7 +162,7 @@ def cpu_baseline(vel, omega, table, gpu_pc_calls):
     return {"value": t_pc * gpu_pc_calls, "unit": "s per RHS (extrapolated)", "cores": cores, "kind": "oracle",
             "sample": f"one FP64 preconditioner application (Algorithm 1) on the full 352^3 workload took "
                       f"{t_pc:.2f} s; scaled by the GPU solve's {gpu_pc_calls} preconditioner calls",
-            "cpu_model": cpu_model(),
+            "cpu_model": cpu_model(), "setup_s": round(t_setup, 2),
             "apply_s": {"sample": "one FP64 A_h apply on the full 352^3 grid", "threads": cores,
                         "s": round(t_ap, 3), "single_thread_s": None if single is None else round(single, 3)}}
 
@@ -194,6 +196,41 @@ def c4_crop_parity(vel, omega, table, src, npml, precision, crop, crop_tol):
     return {"c4": "crop", "crop": f"{crop}^3 + {npml} PML around the source", "precision": precision,
             "gpu_pc_calls": int(its_c), "gpu_relres": float(rel_c), "oracle_pc_calls": its_o,
             "oracle_relres": rel_o, "oracle_s": round(t_or, 1), "rel_l2_error_vs_oracle": err}
+
+
+def c3_crop_parity(vel, omega, table, srcs, npml, crop=64):
+    """The 64-source workload's physics on a crop^3 + npml box holding four of its
+    sources: one batched GPU solve of the four (helm_options.batch = 4, tol 1e-6)
+    against four FP64 oracle solves to 1e-10, relative l2 per source."""
+    import torch
+    from oracle.oracle import Hierarchy as OracleHierarchy
+    from paper_2608_22946_amd import helm
+    from workloads import point_source
+    n = vel.shape[0] - 1
+    ps = np.array(srcs) - npml                      # physical (x, y, z) of every source
+    lo = np.array([int(ps[:, 0].min()), int(ps[:, 1].min()), 0])
+    lo = np.clip(lo - 8, 0, n - crop)
+    inside = [q for q in ps if np.all(q - lo >= 8) and np.all(q - lo <= crop - 8)][:4]
+    vc = np.ascontiguousarray(vel[lo[2]:lo[2] + crop + 1, lo[1]:lo[1] + crop + 1, lo[0]:lo[0] + crop + 1])
+    Nc = crop + 2 * npml
+    fs = np.stack([point_source((Nc,) * 3, tuple(int(v) for v in q - lo + npml), H) for q in inside])
+    Hc = helm.Hierarchy(torch.from_numpy(vc), H, omega, npml, precision="fp32", table=table, device="cuda:0",
+                        batch=len(inside))
+    u, its, rel, rc = Hc.solve(torch.from_numpy(fs.astype(np.complex64)).cuda(), TOL)
+    ug = u.cpu().numpy().astype(np.complex128)
+    Hc.close()
+    O = OracleHierarchy(vc, H, omega, npml, table)
+    errs, t0 = [], time.perf_counter()
+    for k in range(len(inside)):
+        uo, its_o, rel_o, st = O.solve(fs[k], 1e-10)
+        errs.append(float(np.linalg.norm(ug[k] - uo) / np.linalg.norm(uo)))
+        print(json.dumps({"multi_rhs": "oracle crop source", "k": k, "rel_l2_error": errs[-1],
+                          "oracle_s": round(time.perf_counter() - t0, 1)}), flush=True)
+    t_o = time.perf_counter() - t0
+    O.close()
+    return {"crop": f"{crop}^3 + {npml} PML holding {len(inside)} of the sources, one GPU batch",
+            "rel_l2_error_per_source": errs, "gpu_pc_calls": [int(v) for v in its], "oracle_tol": 1e-10,
+            "oracle_s": round(t_o, 1)}
 
 
 # ---- end of the cpu_baseline leg
@@ -308,7 +345,7 @@ def green_pml(cases=((0, 1.119058), (1, 1.119058), (2, 1.119058), (0, 1.5), (0, 
                           "paper_a100_err": 2.4936e-3}), flush=True)
 
 
-def multi_rhs(configs=((1, 1), (4, 1), (1, 4), (1, 8), (2, 4), (2, 8)), seed=3):
+def multi_rhs(configs=((1, 1), (4, 1), (1, 4), (1, 8), (2, 4), (2, 8)), seed=3, with_cpu=False):
     """Many right-hand sides on one hierarchy: 256^3 + 16-cell PML (288^3 total), a seeded
     8-layer model (1500..4000 m/s, sharp interfaces), 64 point sources on an 8 x 8 grid in
     the plane 20 cells below the top of the physical box, FP32, tol 1e-6 per source.
@@ -358,6 +395,8 @@ def multi_rhs(configs=((1, 1), (4, 1), (1, 4), (1, 8), (2, 4), (2, 8)), seed=3):
         Hh.close()
         del Hh, u
         torch.cuda.empty_cache()
+    if with_cpu:
+        print(json.dumps({"multi_rhs": "oracle crop", **c3_crop_parity(vel, omega, table, srcs, npml)}), flush=True)
 
 
 def c4_source(vel, npml, seed=4):
@@ -685,9 +724,9 @@ def main():
                 shape, _, prec = c.partition(":")
                 lanes, batch = (int(v) for v in shape.split("x"))
                 cfgs.append((lanes, batch) + ((prec,) if prec else ()))
-            multi_rhs(tuple(cfgs))
+            multi_rhs(tuple(cfgs), with_cpu=not args.no_cpu_baseline)
         else:
-            multi_rhs()
+            multi_rhs(with_cpu=not args.no_cpu_baseline)
         return
     if args.grad:
         grad_bench(args.steps, args.warmup, args.apply_reps, not args.no_cpu_baseline)
@@ -823,7 +862,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"grf-352-{pr}: 320^3 + 16-cell PML, GRF velocity 2000 m/s +-25% (corr. 20 cells), "
                                "6 ppw at c_min, 1 seeded point source, tol 1e-6",
-                   "grid_total": N_PHYS + 2 * N_PML, "n_pml": N_PML, "nodes_fine": nodes[0], "source": list(src),
+                   "grid_total": N_PHYS + 2 * N_PML, "n_pml": N_PML, "nodes_fine": nodes[0], "nrhs": 1,
+                   "source": list(src),
                    "tol": TOL,
                    "precision": PRECISION_NOTE[pr]},
         "roofline": {"bound": "hbm", "kernel": f"fine-level A_h apply (27-point IOFD, 352^3, {pr})",
@@ -831,7 +871,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(t_apply * 1e3, 4),
-                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                     "counter_GBs": None if traffic is None else round(traffic / t_apply / 1e9, 1),
+                     "counter_frac": None if traffic is None else round(traffic / t_apply / 1e9 / HBM_PEAK_GBS, 4),
+                     "counter_frac_of_copy": None if traffic is None else round(traffic / t_apply / 1e9 / copy_gbs, 4)},
         "pc_calls": int(its),
         "relres": float(rel),
         "solve_per_pc_ms": round(ms_step / max(int(its), 1), 2),
