@@ -103,7 +103,7 @@ typedef struct {
     /* Stencil tiling per level (performance only, results do not depend on it
      * beyond rounding of the fused norms).  helm_setup times the candidates
      * that are not fixed here on options.stream and keeps the fastest. */
-    int tile_tz;              /* z planes per wavefront: 0 = timed; else 2, 4, 8, 16, 32 or 64 */
+    int tile_tz;              /* z planes per wavefront: 0 = timed; else 2..64 */
     int tile_split;           /* -1 = timed; 0 = one launch per stencil; 1 = an interior launch plus
                                  a border launch where the PML layout allows it */
     int lanes;                /* right-hand sides helm_solve runs concurrently (1..8; 0 = 1), each on

@@ -203,7 +203,7 @@ size_t carve(helm_hierarchy *H, char *base, const int N[3], const helm_options &
         Ln.st_hook = c.take<KState>(1);
         size_t np = (size_t)kRedBlocks * 2 * 48;
         for (int l = 0; l < 3; ++l)
-            np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2], kTzCandidates[0]));
+            np = std::max(np, (size_t)stencil_blocks(g[l].n[0], g[l].n[1], g[l].n[2], kTzMin));
         Ln.rb.partials = c.take<double>(np * B);
         Ln.nslot = B;
         Ln.pstride = (long long)np;
@@ -929,9 +929,7 @@ helm_status check_options(const helm_options *o, std::string &msg) {
     }
     if (!in(o->m_4h, 1, kM4Max) || !in(o->c_2h, 1, 8)) { msg = "m_4h must be in 1..8 and c_2h in 1..8"; return HELM_EINVAL; }
     if (!in(o->iofd_K, 1, kKMax)) { msg = "iofd_K must be in 1..128"; return HELM_EINVAL; }
-    bool tz_ok = o->tile_tz == 0;
-    for (int tz : kTzCandidates) tz_ok = tz_ok || o->tile_tz == tz;
-    if (!tz_ok) { msg = "tile_tz must be 0, 2, 4, 8, 16, 32 or 64"; return HELM_EINVAL; }
+    if (o->tile_tz != 0 && !in(o->tile_tz, kTzMin, kTzMax)) { msg = "tile_tz must be 0 or in 2..64"; return HELM_EINVAL; }
     if (!in(o->tile_split, -1, 1)) { msg = "tile_split must be -1, 0 or 1"; return HELM_EINVAL; }
     if (!in(o->lanes, 0, kMaxLanes)) { msg = "lanes must be in 0..8"; return HELM_EINVAL; }
     if (!in(o->pml_variant, 0, 2)) { msg = "pml_variant must be 0, 1 or 2"; return HELM_EINVAL; }
@@ -965,10 +963,12 @@ bool level_ok(int l) { return l >= 0 && l <= 2; }
 // Pick, per level and kernel family, the number of z planes each stencil
 // wavefront marches through and whether the stencils run as one launch or as
 // interior + border launches: time the family's kernel (an operator apply, or a
-// fused two-sweep Jacobi; six launches) with HIP events on the caller's stream,
-// best of two trials, for every candidate and keep the fastest.  Long marches amortise the
-// plane pipeline; short ones give small grids enough workgroups; the split
-// costs a second launch but lets interior tiles run at higher occupancy.
+// fused two-sweep Jacobi; six launches) with HIP events on the caller's stream
+// and keep the fastest.  Long marches amortise the plane pipeline; short ones
+// give small grids enough workgroups, and depths between the powers of two
+// let the last round of workgroups fill the chip.  Every candidate depth is
+// timed as one launch, then the interior + border split (a second launch, but
+// interior tiles at higher occupancy) at the two fastest depths.
 template <typename T>
 hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     Eng<T> E(H);
@@ -979,58 +979,73 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     hipEvent_t a, b;
     HIP_CHK(hipEventCreate(&a));
     HIP_CHK(hipEventCreate(&b));
-    float best = 1e30f;
-    int best_tz = 0, best_split = 0;
-    hipError_t err = hipSuccess;
     auto run = [&]() -> hipError_t {
         return fam == 0 ? E.stencil(l, M_APPLY, l > 0, 0.0, x, nullptr, nullptr, y)
                         : E.stencil(l, M_JAC2, l > 0, H->opt.omega_h, nullptr, x, nullptr, y);
     };
-    for (int cand = 0; cand < 2 * (int)(sizeof(kTzCandidates) / sizeof(int)) && err == hipSuccess; ++cand) {
-        const int tz = kTzCandidates[cand / 2], split = cand % 2;
-        if (tz > H->geom[l].n[2] + 1 && tz != kTzCandidates[0] && H->opt.tile_tz == 0) break;
-        if (tz == 2 && H->geom[l].nn > (1LL << 20) && H->opt.tile_tz == 0) continue;   // never the fastest there
-        if ((H->opt.tile_tz != 0 && tz != H->opt.tile_tz) || (H->opt.tile_split >= 0 && split != H->opt.tile_split))
-            continue;
+    auto time_one = [&](int tz, int split, float &ms) -> hipError_t {
         H->Lf[l].tz[fam] = H->Ld[l].tz[fam] = tz;
         H->Lf[l].split[fam] = H->Ld[l].split[fam] = split;
-        if ((err = run()) != hipSuccess) break;
-        float ms = 1e30f;
+        HIP_CHK(run());
+        ms = 1e30f;
         if (l > 0) {
             // Coarse levels fit the last-level cache when timed back to back, but inside a
             // solve the Krylov bases stream through it in between: time each launch after
             // writing a full fine-level vector (lane 0's outer basis, free during setup).
             float tot = 0.f;
-            for (int r = 0; r < 6 && err == hipSuccess; ++r) {
-                if ((err = launch_fill_zero<T>(static_cast<T *>(H->lane[0].Vout[1]), E.nn(0), H->s)) != hipSuccess)
-                    break;
-                if ((err = hipEventRecord(a, H->s)) != hipSuccess) break;
-                if ((err = run()) != hipSuccess) break;
-                if ((err = hipEventRecord(b, H->s)) != hipSuccess) break;
-                if ((err = hipEventSynchronize(b)) != hipSuccess) break;
+            for (int r = 0; r < 6; ++r) {
+                HIP_CHK(launch_fill_zero<T>(static_cast<T *>(H->lane[0].Vout[1]), E.nn(0), H->s));
+                HIP_CHK(hipEventRecord(a, H->s));
+                HIP_CHK(run());
+                HIP_CHK(hipEventRecord(b, H->s));
+                HIP_CHK(hipEventSynchronize(b));
                 float t = 0.f;
-                if ((err = hipEventElapsedTime(&t, a, b)) != hipSuccess) break;
+                HIP_CHK(hipEventElapsedTime(&t, a, b));
                 tot += t;
             }
             ms = tot;
         } else {
-            for (int trial = 0; trial < 2 && err == hipSuccess; ++trial) {
-                if ((err = hipEventRecord(a, H->s)) != hipSuccess) break;
-                for (int r = 0; r < 6 && err == hipSuccess; ++r) err = run();
-                if (err != hipSuccess || (err = hipEventRecord(b, H->s)) != hipSuccess) break;
-                if ((err = hipEventSynchronize(b)) != hipSuccess) break;
+            for (int trial = 0; trial < 2; ++trial) {
+                HIP_CHK(hipEventRecord(a, H->s));
+                for (int r = 0; r < 6; ++r) HIP_CHK(run());
+                HIP_CHK(hipEventRecord(b, H->s));
+                HIP_CHK(hipEventSynchronize(b));
                 float t = 0.f;
-                if ((err = hipEventElapsedTime(&t, a, b)) != hipSuccess) break;
+                HIP_CHK(hipEventElapsedTime(&t, a, b));
                 ms = std::min(ms, t);
             }
         }
-        if (err != hipSuccess) break;
-        if (ms < best) {
-            best = ms;
-            best_tz = tz;
-            best_split = split;
+        return hipSuccess;
+    };
+    const long long nn = H->geom[l].nn;
+    const int first_split = H->opt.tile_split >= 0 ? H->opt.tile_split : 0;
+    float best = 1e30f, t1 = 1e30f, t2 = 1e30f;   // fastest overall; fastest two depths of the first pass
+    int best_tz = 0, best_split = 0, tz1 = 0, tz2 = 0;
+    hipError_t err = hipSuccess;
+    for (int tz : kTzCandidates) {
+        if (H->opt.tile_tz != 0) {
+            if (tz != kTzCandidates[0]) break;
+            tz = H->opt.tile_tz;
+        } else {
+            const int planes = H->geom[l].n[2] + 1;
+            if (tz > planes && tz != kTzCandidates[0]) break;
+            // short marches pay the plane pipeline's start every few planes: never the fastest on
+            // large levels (unless the level is too thin for longer ones)
+            if ((tz < 4 && nn > (1LL << 20) && planes >= 4) || (tz < 8 && nn > (1LL << 23) && planes >= 8)) continue;
         }
+        float ms = 0.f;
+        if ((err = time_one(tz, first_split, ms)) != hipSuccess) break;
+        if (ms < best) best = ms, best_tz = tz, best_split = first_split;
+        if (ms < t1) t2 = t1, tz2 = tz1, t1 = ms, tz1 = tz;
+        else if (ms < t2) t2 = ms, tz2 = tz;
     }
+    if (err == hipSuccess && H->opt.tile_split < 0)
+        for (int tz : {tz1, tz2}) {
+            if (tz == 0) continue;
+            float ms = 0.f;
+            if ((err = time_one(tz, 1, ms)) != hipSuccess) break;
+            if (ms < best) best = ms, best_tz = tz, best_split = 1;
+        }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     H->Lf[l].tz[fam] = H->Ld[l].tz[fam] = best_tz;

@@ -313,7 +313,9 @@ hipError_t launch_grad_phys(const double *gacc, const Geom &fine, int n_pml, con
                             hipStream_t s);
 
 int stencil_blocks(int nx, int ny, int nz, int tz);   // grid size of launch_stencil on a level (tz 0: default)
-constexpr int kTzCandidates[] = {2, 4, 8, 16, 32, 64};
+// z planes per stencil wavefront: any depth kTzMin..kTzMax may be fixed; setup times the candidates
+constexpr int kTzMin = 2, kTzMax = 64;
+constexpr int kTzCandidates[] = {2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 32, 40, 48, 64};
 
 template <typename TI, typename TO>
 hipError_t launch_convert(const TI *x, TO *y, long long n, hipStream_t s);

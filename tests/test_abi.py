@@ -111,7 +111,7 @@ def test_workspace_grows_linearly_with_batch(L):
 
 
 def test_good_tile_options_accepted(L):
-    for tz in (0, 2, 4, 8, 16, 32, 64):
+    for tz in (0, 2, 3, 6, 8, 12, 16, 24, 32, 64):
         for split in (-1, 0, 1):
             rc, _ = _ws(L, (24, 24, 24), 4, _opts(tile_tz=tz, tile_split=split))
             assert rc == 0, (tz, split)
@@ -119,7 +119,7 @@ def test_good_tile_options_accepted(L):
 
 @pytest.mark.parametrize("field,value", [("m_out", 0), ("m_2h", 13), ("m_4h", 9), ("nJ_h", 0), ("c_2h", 0),
                                          ("iofd_K", 0), ("omega_2h", -0.1), ("struct_size", 8), ("precision", 7),
-                                         ("tile_tz", 3), ("tile_tz", 128), ("tile_split", 2), ("tile_split", -2),
+                                         ("tile_tz", 1), ("tile_tz", 65), ("tile_tz", -1), ("tile_split", 2), ("tile_split", -2),
                                          ("lanes", 9), ("lanes", -1), ("pml_variant", 3), ("pml_variant", -1),
                                          ("batch", 9), ("batch", -1)])
 def test_bad_options_rejected(L, field, value):
