@@ -680,6 +680,33 @@ def c5_bench(n_dirs=8):
     print(json.dumps(out), flush=True)
 
 
+def marked_solve(precision):
+    """One warm solve of the benchmark workload, then one solve between two fills of a
+    12,345-element marker tensor, so that a kernel trace can select that solve's launches."""
+    import torch
+    from paper_2608_22946_amd import helm
+    from workloads import load_iofd_table
+    vel, omega, f_np, src = workload()
+    dev = torch.device("cuda", 0)
+    cdt = torch.complex128 if precision == "fp64" else torch.complex64
+    Hh = helm.Hierarchy(torch.from_numpy(vel), H, omega, N_PML, precision=precision, table=load_iofd_table(),
+                        device=dev)
+    f = torch.from_numpy(f_np).to(dev).to(cdt)
+    u = torch.empty_like(f)
+    Hh.solve(f, TOL, out=u.unsqueeze(0))
+    marker = torch.empty(12345, device=dev)
+    marker.fill_(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, rel, rc = Hh.solve(f, TOL, out=u.unsqueeze(0))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    marker.fill_(2.0)
+    torch.cuda.synchronize()
+    print(json.dumps({"marked_solve_s": round(t, 4), "pc_calls": int(its), "relres": float(rel), "rc": rc,
+                      "precision": precision}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -709,6 +736,8 @@ def main():
     ap.add_argument("--crop", type=int, default=128,
                     help="with --c4: physical cells of the oracle-checked crop around the source (0: none)")
     ap.add_argument("--crop-tol", type=float, default=1e-10, help="with --c4: the oracle's tolerance on the crop")
+    ap.add_argument("--marked-solve", action="store_true",
+                    help="one warm solve, then one solve between two marker fills (for per-launch kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (sharding is a design only).",
@@ -716,6 +745,9 @@ def main():
         sys.exit(2)
     if args.paper_table:
         paper_table()
+        return
+    if args.marked_solve:
+        marked_solve(args.precision)
         return
     if args.multi_rhs:
         if args.multi_rhs_configs:

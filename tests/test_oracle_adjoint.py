@@ -75,19 +75,20 @@ def test_row_derivative_matches_central_difference(oracle_lib, table, op):
 
 def test_gradient_matches_central_difference(oracle_lib, table):
     """dJ/dm for J = Re sum conj(s) u(m), u = Q_h v, A_h v = Q_h f, against
-    (J(m+) - J(m-)) along a random direction, with the PML nodes following their
-    nearest physical node; forward and adjoint solves to 1e-12."""
+    (J(m+) - J(m-)) along eight seeded random directions, with the PML nodes
+    following their nearest physical node; forward and adjoint solves to 1e-12."""
     vel = grf_velocity(8, 4, 4, seed=35, corr_len=2.0).astype(np.float32)
     H0 = oracle_lib.Hierarchy(vel, H, OMEGA, 2, table)
     f = _rand(H0, 0, 36)
     s = _rand(H0, 0, 37)
     g, its, rel, st = H0.grad(f, s, 1e-12)
     assert st == 0 and rel.max() <= 1e-12, (its, rel)
-    Hp, Hm, dm = _perturbed(oracle_lib, table, vel, 1e-5, 38)
-    up, *_ = Hp.solve(f, 1e-12)
-    um, *_ = Hm.solve(f, 1e-12)
-    fd = float(np.real(np.vdot(s, up) - np.vdot(s, um)))
-    an = float(np.sum(g * dm))
-    assert abs(fd - an) <= 1e-5 * abs(fd), (fd, an)
+    for seed in range(38, 46):
+        Hp, Hm, dm = _perturbed(oracle_lib, table, vel, 1e-5, seed)
+        up, *_ = Hp.solve(f, 1e-12)
+        um, *_ = Hm.solve(f, 1e-12)
+        fd = float(np.real(np.vdot(s, up) - np.vdot(s, um)))
+        an = float(np.sum(g * dm))
+        assert abs(fd - an) <= 1e-5 * abs(fd), (seed, fd, an)
     # the physical boundary nodes collect their PML columns: nonzero there
     assert abs(g[0, 4, 4]) > 0 and abs(g[4, 4, 0]) > 0
