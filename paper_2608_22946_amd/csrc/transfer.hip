@@ -14,9 +14,10 @@ namespace {
 template <typename T>
 using real_of = decltype(T{}.re);
 
-// Both kernels run on a 3D grid: 64 x-consecutive nodes per wavefront, four
+// The kernels run on 3D grids: 64 x-consecutive nodes per wavefront, four
 // rows (wavefronts) per block along y, one plane per block along z, so node
-// coordinates come from the launch indices without integer division.
+// coordinates come from the launch indices without integer division (the
+// prolongation's blocks may instead be 32 cells wide and eight rows deep).
 constexpr int kTX = 64, kTY = 4;
 
 // one thread per coarse node; the 27 fine values are read through the cache hierarchy
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(256) k_prolong_add(Geom C, Geom F, const T *__
     using R = std::conditional_t<is_half<TF>(), float, real_of<TF>>;   // FP16-stored vectors add in FP32
     const int sl = blockIdx.z / C.n[2];   // batched slots follow each other along z
     if (slot_off(bt, sl)) return;
-    const int X = blockIdx.x * kTX + threadIdx.x, Y = blockIdx.y * kTY + threadIdx.y, Z = blockIdx.z % C.n[2];
+    const int X = blockIdx.x * blockDim.x + threadIdx.x, Y = blockIdx.y * blockDim.y + threadIdx.y, Z = blockIdx.z % C.n[2];
     if (X >= C.n[0] || Y >= C.n[1]) return;
     c = slot_ptr(c, C.nn, sl);
     f = slot_ptr(f, F.nn, sl);
@@ -152,9 +153,16 @@ namespace {
 dim3 node_grid(const Geom &g, int slots = 1) {
     return dim3((unsigned)((g.n[0] + kTX) / kTX), (unsigned)((g.n[1] + kTY) / kTY), (unsigned)(g.n[2] + 1) * slots);
 }
-// one thread per cell of g: n[0] x n[1] x n[2] (z repeated for each batched slot)
-dim3 cell_grid(const Geom &g, int slots = 1) {
-    return dim3((unsigned)((g.n[0] + kTX - 1) / kTX), (unsigned)((g.n[1] + kTY - 1) / kTY), (unsigned)g.n[2] * slots);
+// one thread per cell of g: n[0] x n[1] x n[2] (z repeated for each batched slot), in blocks of
+// bx x (256 / bx) threads
+dim3 cell_grid(const Geom &g, int bx, int slots = 1) {
+    const int by = 256 / bx;
+    return dim3((unsigned)((g.n[0] + bx - 1) / bx), (unsigned)((g.n[1] + by - 1) / by), (unsigned)g.n[2] * slots);
+}
+// x extent of the prolongation's blocks: 64 cells (a wavefront per row, the widest fine
+// segments), or 32 where that leaves fewer idle lanes (88 cells: 96 lanes against 128)
+int cell_block_x(const Geom &g) {
+    return (g.n[0] + 31) / 32 * 32 < (g.n[0] + 63) / 64 * 64 ? 32 : 64;
 }
 }  // namespace
 
@@ -179,8 +187,9 @@ hipError_t launch_prolong_add(const Geom &coarse, const Geom &fine, const T *c, 
         return hipErrorInvalidValue;
     if ((is_half<T>() && !sc.qs) || (is_half<TF>() && !sf.qs)) return hipErrorInvalidValue;
     const Batch &bt = cur_batch();
-    hipLaunchKernelGGL((k_prolong_add<T, TF>), cell_grid(coarse, bt.n), dim3(kTX, kTY), 0, s, coarse, fine, c, f, sc, sf,
-                       bt);
+    const int bx = cell_block_x(coarse);
+    hipLaunchKernelGGL((k_prolong_add<T, TF>), cell_grid(coarse, bx, bt.n), dim3(bx, 256 / bx), 0, s, coarse, fine, c, f,
+                       sc, sf, bt);
     return hipGetLastError();
 }
 
