@@ -64,6 +64,34 @@ __device__ __forceinline__ Loc<R> locate_at(const LevelArgs<R> &L, float c) {
 
 template <typename R>
 __device__ __forceinline__ R hval(const R *p, R t) { return ((p[3] * t + p[2]) * t + p[1]) * t + p[0]; }
+
+// The five coefficient functions and kappa^2 of the row of node i, from the block's LDS copy
+// `tab` of the level's window of table intervals (kb .. kb + nk - 1).  FP32 levels read the
+// per-node scaled coordinate s (eta* = min(s, K) 0.4 / K, kappa = s kap_s) as their forward
+// stencils do; FP64 levels the velocity.
+template <typename R>
+__device__ __forceinline__ void row_coefs(const LevelArgs<R> &L, const R *tab, long long i, R (&a)[5], R &k2) {
+    R kappa, t;
+    int k;
+    if constexpr (sizeof(R) == sizeof(float)) {
+        const float sv = L.s[i];
+        kappa = (R)sv * L.kap_s;
+        const R u = (R)sv < (R)L.K ? (R)sv : (R)L.K;
+        k = (int)u;
+        k = k < L.K - 1 ? k : L.K - 1;
+        t = u - (R)k;
+    } else {
+        const Loc<R> q = locate_at(L, L.c[i]);
+        kappa = q.kappa;
+        k = q.k;
+        t = q.t;
+    }
+    k = k < L.kb ? L.kb : (k > L.kb + L.nk - 1 ? L.kb + L.nk - 1 : k);
+    const R *p = tab + (k - L.kb) * 20;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) a[f] = hval(p + 4 * f, t);
+    k2 = kappa * kappa;
+}
 template <typename R>
 __device__ __forceinline__ R hdt(const R *p, R t) { return ((R)3 * p[3] * t + (R)2 * p[2]) * t + p[1]; }
 
@@ -162,8 +190,8 @@ constexpr int kTZ = 16;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHN = kHX * kHY;   // staged plane incl. halo
 
 template <typename R, typename TX>
-__device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const TX *__restrict__ x, int X0, int Y0, int z,
-                                            R (*S)[kHN]) {   // S: 9 arrays of kHN
+__device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const R *tab, const TX *__restrict__ x, int X0,
+                                            int Y0, int z, R (*S)[kHN]) {   // S: 9 arrays of kHN
     const int tid = threadIdx.y * kTX + threadIdx.x;
     for (int e = tid; e < kHN; e += kTX * kTY) {
         const int c = e % kHX, r = e / kHX;
@@ -172,12 +200,8 @@ __device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const TX *__r
         if (inside(L, xi, yi, z)) {   // rows exist at interior nodes only; x is zero elsewhere
             const long long i = (long long)z * L.sy + (long long)yi * L.sx + xi;
             const Zc<R> xv = load<R>(x, i);
-            const Loc<R> q = locate_at(L, L.c[i]);
-            const R *p = L.atab + q.k * 20;
-            R a[5];
-#pragma unroll
-            for (int f = 0; f < 5; ++f) a[f] = hval(p + 4 * f, q.t);
-            const R k2 = q.kappa * q.kappa;
+            R a[5], k2;
+            row_coefs(L, tab, i, a, k2);
             v[0] = xv.r;
             v[1] = xv.i;
             v[2] = a[3];
@@ -199,20 +223,16 @@ __device__ __forceinline__ void stage_plane(const LevelArgs<R> &L, const TX *__r
 // u_m = C_m(i) x_i (m = 0..3) and the outputs are plain shell sums of the u_m, with no
 // per-neighbour coefficient arithmetic.
 template <typename R, typename TX, bool SHIFT>
-__device__ __forceinline__ void stage_plane_shell(const LevelArgs<R> &L, const TX *__restrict__ x, int X0, int Y0,
-                                                  int z, R (*S)[kHN]) {
+__device__ __forceinline__ void stage_plane_shell(const LevelArgs<R> &L, const R *tab, const TX *__restrict__ x,
+                                                  int X0, int Y0, int z, R (*S)[kHN]) {
     const int tid = threadIdx.y * kTX + threadIdx.x;
     for (int e = tid; e < kHN; e += kTX * kTY) {
         const int c = e % kHX, r = e / kHX;
         const int xi = X0 - 1 + c, yi = Y0 - 1 + r;
         const long long i = (long long)z * L.sy + (long long)yi * L.sx + xi;   // an interior node
         const Zc<R> xv = load<R>(x, i);
-        const Loc<R> q = locate_at(L, L.c[i]);
-        const R *p = L.atab + q.k * 20;
-        R a[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) a[f] = hval(p + 4 * f, q.t);
-        const R k2 = q.kappa * q.kappa;
+        R a[5], k2;
+        row_coefs(L, tab, i, a, k2);
         const R qq = (R)1 - a[3] - a[4];
         const R M[4] = {a[0], a[1] * (R)(1.0 / 6), a[2] * (R)(1.0 / 12), ((R)1 - a[0] - a[1] - a[2]) * (R)0.125};
         const R C[4] = {(R)6 * a[3] - k2 * M[0], (a[4] - a[3]) - k2 * M[1], (R)0.5 * (qq - a[4]) - k2 * M[2],
@@ -230,6 +250,10 @@ template <typename R, typename TX, typename TG, typename TY, bool SHIFT, bool RE
 __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
                                                 TY *__restrict__ y) {
     __shared__ R S[9][kHN];   // [x.re, x.im, T0..T2, kappa^2 M0..M3][node] of the staged plane
+    extern __shared__ unsigned char smem_raw[];
+    R *tab = reinterpret_cast<R *>(smem_raw);   // the level's window of table intervals
+    for (int e = threadIdx.y * kTX + threadIdx.x; e < L.nk * 20; e += kTX * kTY) tab[e] = L.atab[L.kb * 20 + e];
+    __syncthreads();
     const int X0 = blockIdx.x * kTX, Y0 = blockIdx.y * kTY, Zb = blockIdx.z * kTZ;
     const int X = X0 + threadIdx.x, Y = Y0 + threadIdx.y;
     const int Ze = min(Zb + kTZ, L.nz + 1);
@@ -249,7 +273,7 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
     Zc<R> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
     for (int p = Zb - 1; p <= Ze; ++p) {
         if (shell) {
-            stage_plane_shell<R, TX, SHIFT>(L, x, X0, Y0, p, S);
+            stage_plane_shell<R, TX, SHIFT>(L, tab, x, X0, Y0, p, S);
             __syncthreads();
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
@@ -267,7 +291,7 @@ __global__ void __launch_bounds__(256) k_apply_t(LevelArgs<R> L, const TX *__res
                     acc[2].i += u1i;
                 }
         } else {
-        stage_plane(L, x, X0, Y0, p, S);
+        stage_plane(L, tab, x, X0, Y0, p, S);
         __syncthreads();
         if (inxy && p >= 1 && p <= L.nz - 1) {   // only interior planes hold rows
             // z weights of row plane p seen from output plane p - dz: w_z(p, -dz)
@@ -485,7 +509,8 @@ template <typename R, typename TX, typename TG, typename TY>
 hipError_t launch_apply_t(const LevelArgs<R> &L, int shifted, const TX *x, const TG *g, TY *y, hipStream_t s) {
     const dim3 grid((unsigned)((L.nx + kTX) / kTX), (unsigned)((L.ny + kTY) / kTY), (unsigned)((L.nz + kTZ) / kTZ));
     const dim3 blk(kTX, kTY);
-#define HELM_AT(SH, RS) hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, SH, RS>), grid, blk, 0, s, L, x, g, y)
+    const size_t shm = sizeof(R) * L.nk * 20;
+#define HELM_AT(SH, RS) hipLaunchKernelGGL((k_apply_t<R, TX, TG, TY, SH, RS>), grid, blk, shm, s, L, x, g, y)
     if (g) {
         if (shifted) HELM_AT(true, true); else HELM_AT(false, true);
     } else {
