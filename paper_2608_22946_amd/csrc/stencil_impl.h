@@ -351,7 +351,7 @@ __device__ __forceinline__ Z<R> row_value(const LevelArgs<R> &L, const R *stab, 
 }
 
 __device__ __forceinline__ void block_reduce_store(double v, double *dst) {
-    // wavefront sum (DPP), then across the 4 waves through LDS
+    // wavefront sum (DPP), then across the workgroup's waves through LDS
     v = wave_sum_f64(v);
     __shared__ double red[kWavesY];
     int w = threadIdx.y, l = threadIdx.x;
@@ -367,18 +367,20 @@ __device__ __forceinline__ void block_reduce_store(double v, double *dst) {
 
 // Last-block epilogue of a stencil with fused ||y||^2: beta, state reset.
 __device__ void norm_epilogue(const RedBuf &rb, int nblocks, KState *st) {
+    constexpr int nt = 64 * kWavesY;   // threads of a stencil workgroup
+    static_assert((nt & (nt - 1)) == 0, "the tree sum needs a power-of-two workgroup");
     __shared__ bool last;
-    __shared__ double red[256];
+    __shared__ double red[nt];
     const int tid = threadIdx.x + 64 * threadIdx.y;
     if (tid == 0) last = take_ticket(rb.counter, nblocks);
     __syncthreads();
     if (!last) return;
     double s = 0;
 #pragma unroll 8
-    for (int b = tid; b < nblocks; b += 256) s += partial_load(rb.partials + b);
+    for (int b = tid; b < nblocks; b += nt) s += partial_load(rb.partials + b);
     red[tid] = s;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = nt / 2; off > 0; off >>= 1) {
         if (tid < off) red[tid] += red[tid + off];
         __syncthreads();
     }
@@ -644,7 +646,7 @@ struct TileMap {
 };
 
 template <typename R, typename TX, typename TG, typename TY, int MODE, bool SHIFT, bool NORM, int PART>
-__global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
+__global__ void __launch_bounds__(64 * kWavesY) k_stencil(LevelArgs<R> L, const TX *__restrict__ x, const TG *__restrict__ g,
                                                  const TY *__restrict__ base, TY *__restrict__ y, R omegaJ, TileMap M,
                                                  RedBuf rb, KState *st, Scales sc, Batch bt) {
     // XCD-aware order of (tile, slot) pairs: block b runs on XCD b % 8; each XCD takes a
@@ -676,9 +678,9 @@ __global__ void __launch_bounds__(256) k_stencil(LevelArgs<R> L, const TX *__res
     R *stab = reinterpret_cast<R *>(smem_raw);   // alpha pieces, then (FP32) the shell quintics
     const int tid = threadIdx.x + 64 * threadIdx.y;
     // the level's window of table intervals only (at 4h almost every node is in the clamped one)
-    for (int i = tid; i < L.nk * 20; i += 256) stab[i] = L.atab[L.kb * 20 + i];
+    for (int i = tid; i < L.nk * 20; i += 64 * kWavesY) stab[i] = L.atab[L.kb * 20 + i];
     if (scaled_coordinate<R>())
-        for (int i = tid; i < L.nck * 24; i += 256) stab[L.nk * 20 + i] = L.ctab[L.cb * 24 + i];
+        for (int i = tid; i < L.nck * 24; i += 64 * kWavesY) stab[L.nk * 20 + i] = L.ctab[L.cb * 24 + i];
     __syncthreads();
 
     const int ntx = M.ntx, nty = M.nty;
