@@ -275,6 +275,22 @@ helm_status helm_vec_dots(helm_hierarchy *H, int level, int k, const void *const
 helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const void *const *V, void *w,
                                     double *out);
 
+/* Tile choices that helm_setup has timed in this process (per GPU architecture, precision, level
+ * shape and kernel family: the z depth of the stencil wavefronts and whether a stencil runs as one
+ * launch or two), written to or read from a text file, so that a later process reuses them instead of
+ * timing again (the timing is most of a first setup).  Performance only: results depend on the
+ * choices no more than through the rounding order of fused norms.
+ *   helm_tiles_save  writes every choice made or loaded so far in this process to `path` (a header
+ *                    line, then one line per choice).
+ *   helm_tiles_load  adds the choices in `path` whose architecture is that of a visible GPU to this
+ *                    process's table, for every such GPU, replacing equal keys; `n_loaded` (optional,
+ *                    HOST int) receives the number of entries added or replaced.
+ * Both return HELM_EINVAL (message in helm_last_error(NULL)) for a NULL path, a file that cannot be
+ * opened or written, or (load) a file that is not a tile-choice file or has a malformed line; choices
+ * read before a malformed line stay loaded. */
+helm_status helm_tiles_save(const char *path);
+helm_status helm_tiles_load(const char *path, int *n_loaded);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): helm_vec_dots on plain
  * vectors, without a hierarchy, with the result left in device memory.  The

@@ -1469,6 +1469,101 @@ void helm_destroy(helm_hierarchy *H) {
 
 const char *helm_last_error(const helm_hierarchy *H) { return H ? H->err.c_str() : g_thread_error.c_str(); }
 
+// Tile-choice file: a header line, then one line per choice:
+//   <arch> <precision> <family> <tile_tz option> <tile_split option> <n0> <n1> <n2> <z depth> <split>
+// <arch> is the GPU's architecture name up to its first ':' (e.g. gfx950).
+static const char *const kTileHeader = "# helm tile choices v1";
+
+static std::string device_arch(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return std::string();
+    std::string a(p.gcnArchName);
+    return a.substr(0, a.find(':'));
+}
+
+helm_status helm_tiles_save(const char *path) {
+    if (!path) return fail(nullptr, HELM_EINVAL, "path is NULL");
+    std::vector<std::pair<TileKey, std::pair<int, int>>> entries;
+    {
+        std::lock_guard<std::mutex> lock(g_tile_mutex);
+        entries.assign(g_tile_cache.begin(), g_tile_cache.end());
+    }
+    FILE *fp = std::fopen(path, "w");
+    if (!fp) return fail(nullptr, HELM_EINVAL, std::string("cannot write ") + path);
+    bool ok = std::fprintf(fp, "%s\n", kTileHeader) > 0;
+    for (const auto &e : entries) {
+        const TileKey &k = e.first;
+        const std::string arch = device_arch(k.dev);
+        if (arch.empty()) continue;
+        ok = ok && std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d\n", arch.c_str(), k.prec, k.fam, k.tz_opt,
+                                k.split_opt, k.n[0], k.n[1], k.n[2], e.second.first, e.second.second) > 0;
+    }
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(nullptr, HELM_EINVAL, std::string("error writing ") + path);
+    return HELM_OK;
+}
+
+helm_status helm_tiles_load(const char *path, int *n_loaded) {
+    if (n_loaded) *n_loaded = 0;
+    if (!path) return fail(nullptr, HELM_EINVAL, "path is NULL");
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return fail(nullptr, HELM_EINVAL, std::string("cannot read ") + path);
+    // visible GPUs by architecture (none without a GPU: the file is still checked)
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    std::vector<std::string> archs;
+    for (int d = 0; d < ndev; ++d) archs.push_back(device_arch(d));
+    char line[512];
+    int lineno = 0, added = 0;
+    helm_status st = HELM_OK;
+    std::string msg;
+    while (std::fgets(line, sizeof line, fp)) {
+        ++lineno;
+        if (lineno == 1) {
+            if (std::strncmp(line, kTileHeader, std::strlen(kTileHeader)) != 0) {
+                st = HELM_EINVAL;
+                msg = std::string(path) + ": not a tile-choice file";
+                break;
+            }
+            continue;
+        }
+        char arch[64];
+        int v[9], tail = 0;
+        const int got = std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %n", arch, &v[0], &v[1], &v[2], &v[3],
+                                    &v[4], &v[5], &v[6], &v[7], &v[8], &tail);
+        const bool valid = got == 10 && line[tail] == '\0' && v[0] >= HELM_FP64 && v[0] <= HELM_MIXED &&
+                           (v[1] == 0 || v[1] == 1) && (v[2] == 0 || (v[2] >= kTzMin && v[2] <= kTzMax)) &&
+                           v[3] >= -1 && v[3] <= 1 && v[4] >= 2 && v[5] >= 2 && v[6] >= 2 && v[7] >= kTzMin &&
+                           v[7] <= kTzMax && (v[8] == 0 || v[8] == 1);
+        if (!valid) {
+            st = HELM_EINVAL;
+            msg = std::string(path) + ": malformed line " + std::to_string(lineno);
+            break;
+        }
+        for (int d = 0; d < ndev; ++d) {
+            if (archs[d] != arch) continue;
+            TileKey key;
+            std::memset(&key, 0, sizeof(key));
+            key.dev = d;
+            key.prec = v[0];
+            key.fam = v[1];
+            key.tz_opt = v[2];
+            key.split_opt = v[3];
+            for (int a = 0; a < 3; ++a) key.n[a] = v[4 + a];
+            std::lock_guard<std::mutex> lock(g_tile_mutex);
+            g_tile_cache[key] = {v[7], v[8]};
+            ++added;
+        }
+    }
+    std::fclose(fp);
+    if (n_loaded) *n_loaded = added;
+    if (st == HELM_OK && lineno == 0) {
+        st = HELM_EINVAL;
+        msg = std::string(path) + ": empty file";
+    }
+    return st == HELM_OK ? HELM_OK : fail(nullptr, st, msg);
+}
+
 helm_status helm_dims(const helm_hierarchy *H, int level, int dims[3]) {
     if (!H || !dims || !level_ok(level)) return fail(const_cast<helm_hierarchy *>(H), HELM_EINVAL, "invalid arguments");
     for (int a = 0; a < 3; ++a) dims[a] = H->geom[level].n[a];

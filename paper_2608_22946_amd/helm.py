@@ -43,7 +43,8 @@ EXPORTED = ["helm_default_options", "helm_workspace_size", "helm_setup", "helm_s
             "helm_last_error", "helm_dims", "helm_apply", "helm_residual", "helm_residual_restrict", "helm_jacobi",
             "helm_restrict",
             "helm_prolong_add", "helm_bottom", "helm_vcycle", "helm_coarse_solve", "helm_smooth", "helm_precond",
-            "helm_vec_dots", "helm_vec_orthonormalize", "helm_vec_dots_static"]
+            "helm_vec_dots", "helm_vec_orthonormalize", "helm_vec_dots_static", "helm_tiles_save",
+            "helm_tiles_load"]
 
 _lib = None
 
@@ -81,6 +82,8 @@ def lib():
         L.helm_vec_dots.argtypes = [P, I, I, P, P, P]
         L.helm_vec_orthonormalize.argtypes = [P, I, I, P, P, P]
         L.helm_vec_dots_static.argtypes = [I, ctypes.c_longlong, I, P, P, P, P]
+        L.helm_tiles_save.argtypes = [ctypes.c_char_p]
+        L.helm_tiles_load.argtypes = [ctypes.c_char_p, P]
         _lib = L
     return _lib
 
@@ -368,6 +371,19 @@ def vec_dots_static(V, w, out=None):
     stream = torch.cuda.current_stream(w.device).cuda_stream
     _check(lib().helm_vec_dots_static(prec, w.numel(), k, arr, _ptr(w), _ptr(out), ctypes.c_void_p(stream)))
     return out
+
+
+def tiles_save(path):
+    """helm_tiles_save: write the stencil tile choices timed (or loaded) so far in this process."""
+    _check(lib().helm_tiles_save(os.fsencode(path)))
+
+
+def tiles_load(path):
+    """helm_tiles_load: reuse tile choices saved by an earlier process on the same GPU architecture;
+    returns the number of entries added or replaced."""
+    n = ctypes.c_int(0)
+    _check(lib().helm_tiles_load(os.fsencode(path), ctypes.addressof(n)))
+    return n.value
 
 
 class _Solve(torch.autograd.Function):

@@ -182,3 +182,33 @@ def test_static_dots_rejects_arguments_on_host(L):
     assert L.helm_vec_dots_static(helm.FP32, 10, 13, None, w, w, None) == -1  # k > 12
     assert L.helm_vec_dots_static(helm.FP32, 10, 2, None, w, w, None) == -1   # V missing
     assert L.helm_vec_dots_static(helm.FP64, 10, 0, None, w, None, None) == -1  # out missing
+
+
+def test_tile_file_checked_on_the_cpu(L, tmp_path):
+    """helm_tiles_load reads and checks a tile-choice file without a GPU (nothing matches an
+    architecture then); bad paths, foreign files and malformed lines are rejected."""
+    n = ctypes.c_int(-1)
+    good = tmp_path / "tiles.txt"
+    good.write_text("# helm tile choices v1\n"
+                    "gfx950 1 0 0 -1 352 352 352 24 0\n"
+                    "gfx950 1 1 0 -1 176 176 176 12 1\n")
+    assert L.helm_tiles_load(str(good).encode(), ctypes.addressof(n)) == 0 and n.value == 0
+    assert L.helm_tiles_load(None, None) == -1
+    assert L.helm_tiles_save(None) == -1
+    assert L.helm_tiles_load(str(tmp_path / "missing.txt").encode(), None) == -1
+    assert L.helm_tiles_save(str(tmp_path / "no" / "such" / "dir.txt").encode()) == -1
+    for bad in ["gfx950 1 0 0 -1 352 352 352 24 0\n",                                   # no header
+                "# helm tile choices v1\ngfx950 1 0 0 -1 352 352 352 24\n",              # field missing
+                "# helm tile choices v1\ngfx950 1 0 0 -1 352 352 352 65 0\n",            # depth > 64
+                "# helm tile choices v1\ngfx950 3 0 0 -1 352 352 352 24 0\n",            # precision
+                "# helm tile choices v1\ngfx950 1 0 0 -1 352 352 352 24 0 7\n",          # trailing field
+                ""]:
+        f = tmp_path / "bad.txt"
+        f.write_text(bad)
+        assert L.helm_tiles_load(str(f).encode(), None) == -1, bad
+        assert L.helm_last_error(None)
+    # saving an empty table writes the header alone, which loads again
+    out = tmp_path / "saved.txt"
+    assert L.helm_tiles_save(str(out).encode()) == 0
+    assert out.read_text().splitlines()[0] == "# helm tile choices v1"
+    assert L.helm_tiles_load(str(out).encode(), ctypes.addressof(n)) == 0 and n.value == 0
