@@ -276,8 +276,8 @@ helm_status helm_vec_orthonormalize(helm_hierarchy *H, int level, int k, const v
                                     double *out);
 
 /* Tile choices that helm_setup has timed in this process (per GPU architecture, precision, level
- * shape and kernel family: the z depth of the stencil wavefronts and whether a stencil runs as one
- * launch or two), written to or read from a text file, so that a later process reuses them instead of
+ * shape, kernel family and batch slots: the z depth of the stencil wavefronts and whether a stencil
+ * runs as one launch or two), written to or read from a text file, so that a later process reuses them instead of
  * timing again (the timing is most of a first setup).  Performance only: results depend on the
  * choices no more than through the rounding order of fused norms.
  *   helm_tiles_save  writes every choice made or loaded so far in this process to `path` (a header

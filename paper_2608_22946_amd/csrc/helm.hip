@@ -979,6 +979,13 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     hipEvent_t a, b;
     HIP_CHK(hipEventCreate(&a));
     HIP_CHK(hipEventCreate(&b));
+    // every slot of the lane runs, as in a batched solve (more workgroups per launch favour
+    // longer marches)
+    Batch tb;
+    tb.n = H->lane[0].nslot;
+    tb.mask = (1u << tb.n) - 1u;
+    tb.pstride = H->lane[0].pstride;
+    BatchScope tscope(tb);
     auto run = [&]() -> hipError_t {
         return fam == 0 ? E.stencil(l, M_APPLY, l > 0, 0.0, x, nullptr, nullptr, y)
                         : E.stencil(l, M_JAC2, l > 0, H->opt.omega_h, nullptr, x, nullptr, y);
@@ -1053,11 +1060,11 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
     return err;
 }
 
-// Tile choices already timed in this process, per device, precision, level shape and
-// kernel family (and the options that restrict the candidates): a later setup of the
-// same shape reuses them instead of timing again.
+// Tile choices already timed in this process, per device, precision, level shape, kernel
+// family and batch slots (and the options that restrict the candidates): a later setup of
+// the same shape reuses them instead of timing again.
 struct TileKey {
-    int dev, prec, fam, tz_opt, split_opt, n[3];
+    int dev, prec, fam, tz_opt, split_opt, slots, n[3];
     bool operator<(const TileKey &o) const {
         return std::memcmp(this, &o, sizeof(TileKey)) < 0;
     }
@@ -1085,6 +1092,7 @@ hipError_t tune_tiles(helm_hierarchy *H) {
             key.fam = f;
             key.tz_opt = H->opt.tile_tz;
             key.split_opt = H->opt.tile_split;
+            key.slots = H->lane[0].nslot;
             for (int a = 0; a < 3; ++a) key.n[a] = H->geom[l].n[a];
             {
                 std::lock_guard<std::mutex> lock(g_tile_mutex);
@@ -1470,9 +1478,9 @@ void helm_destroy(helm_hierarchy *H) {
 const char *helm_last_error(const helm_hierarchy *H) { return H ? H->err.c_str() : g_thread_error.c_str(); }
 
 // Tile-choice file: a header line, then one line per choice:
-//   <arch> <precision> <family> <tile_tz option> <tile_split option> <n0> <n1> <n2> <z depth> <split>
+//   <arch> <precision> <family> <tile_tz option> <tile_split option> <slots> <n0> <n1> <n2> <z depth> <split>
 // <arch> is the GPU's architecture name up to its first ':' (e.g. gfx950).
-static const char *const kTileHeader = "# helm tile choices v1";
+static const char *const kTileHeader = "# helm tile choices v2";
 
 static std::string device_arch(int dev) {
     hipDeviceProp_t p;
@@ -1495,8 +1503,8 @@ helm_status helm_tiles_save(const char *path) {
         const TileKey &k = e.first;
         const std::string arch = device_arch(k.dev);
         if (arch.empty()) continue;
-        ok = ok && std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d\n", arch.c_str(), k.prec, k.fam, k.tz_opt,
-                                k.split_opt, k.n[0], k.n[1], k.n[2], e.second.first, e.second.second) > 0;
+        ok = ok && std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d %d\n", arch.c_str(), k.prec, k.fam, k.tz_opt,
+                                k.split_opt, k.slots, k.n[0], k.n[1], k.n[2], e.second.first, e.second.second) > 0;
     }
     ok = (std::fclose(fp) == 0) && ok;
     if (!ok) return fail(nullptr, HELM_EINVAL, std::string("error writing ") + path);
@@ -1528,13 +1536,13 @@ helm_status helm_tiles_load(const char *path, int *n_loaded) {
             continue;
         }
         char arch[64];
-        int v[9], tail = 0;
-        const int got = std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %n", arch, &v[0], &v[1], &v[2], &v[3],
-                                    &v[4], &v[5], &v[6], &v[7], &v[8], &tail);
-        const bool valid = got == 10 && line[tail] == '\0' && v[0] >= HELM_FP64 && v[0] <= HELM_MIXED &&
+        int v[10], tail = 0;
+        const int got = std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %n", arch, &v[0], &v[1], &v[2],
+                                    &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &tail);
+        const bool valid = got == 11 && line[tail] == '\0' && v[0] >= HELM_FP64 && v[0] <= HELM_MIXED &&
                            (v[1] == 0 || v[1] == 1) && (v[2] == 0 || (v[2] >= kTzMin && v[2] <= kTzMax)) &&
-                           v[3] >= -1 && v[3] <= 1 && v[4] >= 2 && v[5] >= 2 && v[6] >= 2 && v[7] >= kTzMin &&
-                           v[7] <= kTzMax && (v[8] == 0 || v[8] == 1);
+                           v[3] >= -1 && v[3] <= 1 && v[4] >= 1 && v[4] <= kMaxBatch && v[5] >= 2 && v[6] >= 2 &&
+                           v[7] >= 2 && v[8] >= kTzMin && v[8] <= kTzMax && (v[9] == 0 || v[9] == 1);
         if (!valid) {
             st = HELM_EINVAL;
             msg = std::string(path) + ": malformed line " + std::to_string(lineno);
@@ -1549,9 +1557,10 @@ helm_status helm_tiles_load(const char *path, int *n_loaded) {
             key.fam = v[1];
             key.tz_opt = v[2];
             key.split_opt = v[3];
-            for (int a = 0; a < 3; ++a) key.n[a] = v[4 + a];
+            key.slots = v[4];
+            for (int a = 0; a < 3; ++a) key.n[a] = v[5 + a];
             std::lock_guard<std::mutex> lock(g_tile_mutex);
-            g_tile_cache[key] = {v[7], v[8]};
+            g_tile_cache[key] = {v[8], v[9]};
             ++added;
         }
     }

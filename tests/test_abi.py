@@ -189,19 +189,21 @@ def test_tile_file_checked_on_the_cpu(L, tmp_path):
     architecture then); bad paths, foreign files and malformed lines are rejected."""
     n = ctypes.c_int(-1)
     good = tmp_path / "tiles.txt"
-    good.write_text("# helm tile choices v1\n"
-                    "gfx950 1 0 0 -1 352 352 352 24 0\n"
-                    "gfx950 1 1 0 -1 176 176 176 12 1\n")
+    good.write_text("# helm tile choices v2\n"
+                    "gfx950 1 0 0 -1 1 352 352 352 24 0\n"
+                    "gfx950 1 1 0 -1 8 176 176 176 12 1\n")
     assert L.helm_tiles_load(str(good).encode(), ctypes.addressof(n)) == 0 and n.value == 0
     assert L.helm_tiles_load(None, None) == -1
     assert L.helm_tiles_save(None) == -1
     assert L.helm_tiles_load(str(tmp_path / "missing.txt").encode(), None) == -1
     assert L.helm_tiles_save(str(tmp_path / "no" / "such" / "dir.txt").encode()) == -1
-    for bad in ["gfx950 1 0 0 -1 352 352 352 24 0\n",                                   # no header
-                "# helm tile choices v1\ngfx950 1 0 0 -1 352 352 352 24\n",              # field missing
-                "# helm tile choices v1\ngfx950 1 0 0 -1 352 352 352 65 0\n",            # depth > 64
-                "# helm tile choices v1\ngfx950 3 0 0 -1 352 352 352 24 0\n",            # precision
-                "# helm tile choices v1\ngfx950 1 0 0 -1 352 352 352 24 0 7\n",          # trailing field
+    for bad in ["gfx950 1 0 0 -1 1 352 352 352 24 0\n",                                 # no header
+                "# helm tile choices v1\ngfx950 1 0 0 -1 352 352 352 24 0\n",            # older format
+                "# helm tile choices v2\ngfx950 1 0 0 -1 1 352 352 352 24\n",            # field missing
+                "# helm tile choices v2\ngfx950 1 0 0 -1 1 352 352 352 65 0\n",          # depth > 64
+                "# helm tile choices v2\ngfx950 3 0 0 -1 1 352 352 352 24 0\n",          # precision
+                "# helm tile choices v2\ngfx950 1 0 0 -1 9 352 352 352 24 0\n",          # slots > 8
+                "# helm tile choices v2\ngfx950 1 0 0 -1 1 352 352 352 24 0 7\n",        # trailing field
                 ""]:
         f = tmp_path / "bad.txt"
         f.write_text(bad)
@@ -210,5 +212,5 @@ def test_tile_file_checked_on_the_cpu(L, tmp_path):
     # saving an empty table writes the header alone, which loads again
     out = tmp_path / "saved.txt"
     assert L.helm_tiles_save(str(out).encode()) == 0
-    assert out.read_text().splitlines()[0] == "# helm tile choices v1"
+    assert out.read_text().splitlines()[0] == "# helm tile choices v2"
     assert L.helm_tiles_load(str(out).encode(), ctypes.addressof(n)) == 0 and n.value == 0
