@@ -1001,7 +1001,10 @@ hipError_t tune_level_tiles(helm_hierarchy *H, int l, int fam) {
             // writing a full fine-level vector (lane 0's outer basis, free during setup).
             float tot = 0.f;
             for (int r = 0; r < 6; ++r) {
-                HIP_CHK(launch_fill_zero<T>(static_cast<T *>(H->lane[0].Vout[1]), E.nn(0), H->s));
+                {
+                    BatchScope one{Batch{}};   // one fine vector is enough to evict the coarse level
+                    HIP_CHK(launch_fill_zero<T>(static_cast<T *>(H->lane[0].Vout[1]), E.nn(0), H->s));
+                }
                 HIP_CHK(hipEventRecord(a, H->s));
                 HIP_CHK(run());
                 HIP_CHK(hipEventRecord(b, H->s));
