@@ -13,10 +13,9 @@ int stencil_blocks(int nx, int ny, int nz, int tz) {
 
 template <typename R, typename TI, typename TO>
 hipError_t launch_qapply(const LevelArgs<R> &L, const TI *x, TO *y, hipStream_t s) {
-    const long long nn = (long long)(L.nz + 1) * L.sy;
-    int blocks = (int)std::min<long long>((nn + 255) / 256, 65536);
-    hipLaunchKernelGGL((k_qapply<R, TI, TO>), dim3(blocks, cur_batch().n), dim3(256), sizeof(R) * L.K * 12, s, L, x, y,
-                       cur_batch());
+    const int ntx = ceil_div(L.nx + 1, kQX), nty = ceil_div(L.ny + 1, 4), nzc = ceil_div(L.nz + 1, kQZ);
+    hipLaunchKernelGGL((k_qapply<R, TI, TO>), dim3(ntx * nty, nzc, cur_batch().n), dim3(64, 4), sizeof(R) * L.K * 12, s,
+                       L, x, y, cur_batch());
     return hipGetLastError();
 }
 

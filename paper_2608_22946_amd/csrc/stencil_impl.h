@@ -790,47 +790,105 @@ __global__ void __launch_bounds__(64 * kWavesY) k_stencil(LevelArgs<R> L, const 
     }
 }
 
-// Amplitude correction Q_h (eq. q-operator): shell weights from beta at the
-// fine-grid eta*, no stretching and no ell^-2.  Used twice per solve, so a
-// plain one-thread-per-node gather is enough.
+// Amplitude correction Q_h (eq. q-operator): row i takes the shell weights of its own node
+// (from beta at the fine-grid eta*) on its interior neighbours, with no stretching and no
+// ell^-2.  One wavefront per row y at 64 consecutive x (outputs on lanes 1..62, neighbours
+// x -+ 1 through DPP), marching kQZ planes in z: every plane gives its in-plane shell sums of
+// the interior values, S0 (centre), S1 (four faces) and S2 (four corners), and output plane z
+// takes Q0 S0(z) + Q1 (S1(z) + S0(z-+1)) + Q2 (S2(z) + S1(z-+1)) + Q3 S2(z-+1).  The loads of
+// plane p + 1 are issued before plane p is summed.
+constexpr int kQZ = 16, kQX = 62;
+
+template <typename R>
+struct QSums {
+    Z<R> s0, s1, s2;
+};
+
 template <typename R, typename TI, typename TO>
 __global__ void __launch_bounds__(256) k_qapply(LevelArgs<R> L, const TI *__restrict__ x, TO *__restrict__ y,
                                                Batch bt) {
-    if (slot_off(bt, blockIdx.y)) return;
-    x = slot_ptr(x, (long long)(L.nz + 1) * L.sy, blockIdx.y);
-    y = slot_ptr(y, (long long)(L.nz + 1) * L.sy, blockIdx.y);
+    const int sl = blockIdx.z;   // batched right-hand side
+    if (slot_off(bt, sl)) return;
+    const long long nn = (long long)(L.nz + 1) * L.sy;
+    x = slot_ptr(x, nn, sl);
+    y = slot_ptr(y, nn, sl);
     extern __shared__ unsigned char smem_raw[];
     R *btab = reinterpret_cast<R *>(smem_raw);
-    for (int i = threadIdx.x; i < L.K * 12; i += blockDim.x) btab[i] = L.btab[i];
+    for (int i = threadIdx.x + 64 * threadIdx.y; i < L.K * 12; i += 256) btab[i] = L.btab[i];
     __syncthreads();
-    const long long nn = (long long)(L.nz + 1) * L.sy;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
-        const int xi = (int)(i % L.sx);
-        const int yi = (int)((i / L.sx) % (L.ny + 1));
-        const int zi = (int)(i / L.sy);
-        Z<R> acc = {0, 0};
-        if (xi >= 1 && xi <= L.nx - 1 && yi >= 1 && yi <= L.ny - 1 && zi >= 1 && zi <= L.nz - 1) {
+    const int ntx = (L.nx + kQX) / kQX;   // x tiles covering nodes 0..nx
+    const int xt = blockIdx.x % ntx, yt = blockIdx.x / ntx;
+    const int lane = threadIdx.x, yg = yt * 4 + threadIdx.y;
+    const int xg = xt * kQX - 1 + lane;
+    if (yg > L.ny) return;   // whole wavefronts leave; no barrier follows
+    const int z0 = blockIdx.y * kQZ, z1 = min(z0 + kQZ, L.nz + 1);
+    const bool x_int = xg >= 1 && xg <= L.nx - 1;
+    const bool out_lane = lane >= 1 && lane <= kQX && xg <= L.nx;
+    const int xc = min(max(xg, 0), L.nx);
+    const int ym = max(yg - 1, 0), yp = min(yg + 1, L.ny);
+    const bool rm_ok = x_int && yg - 1 >= 1, r0_ok = x_int && yg >= 1 && yg <= L.ny - 1, rp_ok = x_int && yg + 1 <= L.ny - 1;
+    const long long om = (long long)ym * L.sx + xc, o0 = (long long)yg * L.sx + xc, op = (long long)yp * L.sx + xc;
+    const Z<R> zero = {0, 0};
+    struct Raw {
+        TI a, b, c;
+    };
+    auto issue = [&](int p, Raw &r) {
+        const long long base = (long long)min(max(p, 0), L.nz) * L.sy;
+        r.a = x[base + om];
+        r.b = x[base + o0];
+        r.c = x[base + op];
+    };
+    auto sums = [&](int p, const Raw &r) {
+        const bool zok = p >= 1 && p <= L.nz - 1;
+        const Z<R> a = (zok && rm_ok) ? Z<R>{(R)r.a.re, (R)r.a.im} : zero;
+        const Z<R> b = (zok && r0_ok) ? Z<R>{(R)r.b.re, (R)r.b.im} : zero;
+        const Z<R> c = (zok && rp_ok) ? Z<R>{(R)r.c.re, (R)r.c.im} : zero;
+        const Z<R> col = zadd(a, c);
+        QSums<R> q;
+        q.s0 = b;
+        q.s1 = zadd(col, zadd(zleft(b), zright(b)));
+        q.s2 = zadd(zleft(col), zright(col));
+        return q;
+    };
+    auto emit = [&](int z, const QSums<R> &m, const QSums<R> &o, const QSums<R> &p) {
+        if (!out_lane || z < z0 || z >= z1) return;
+        Z<R> acc = zero;
+        if (r0_ok && z >= 1 && z <= L.nz - 1) {
             R kappa, t;
             int k;
-            locate(L, L.c[i], kappa, k, t);
-            const R *p = btab + k * 12;
-            const R b1 = horner(p, t), b2 = horner(p + 4, t), b3 = horner(p + 8, t);
+            locate(L, L.c[(long long)z * L.sy + o0], kappa, k, t);
+            const R *bp = btab + k * 12;
+            const R b1 = horner(bp, t), b2 = horner(bp + 4, t), b3 = horner(bp + 8, t);
             const R Q[4] = {b1, b2 * (R)(1.0 / 6), b3 * (R)(1.0 / 12), ((R)1 - b1 - b2 - b3) * (R)0.125};
-            Z<R> S[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-            for (int dz = -1; dz <= 1; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        const int xx = xi + dx, yy = yi + dy, zz = zi + dz;
-                        if (xx < 1 || xx > L.nx - 1 || yy < 1 || yy > L.ny - 1 || zz < 1 || zz > L.nz - 1) continue;
-                        const int sh = (dx != 0) + (dy != 0) + (dz != 0);
-                        S[sh] = zadd(S[sh], ld<R>(x, i + dx + dy * L.sx + dz * L.sy));
-                    }
-            for (int m = 0; m < 4; ++m) acc = zadd(acc, zscale(Q[m], S[m]));
+            acc = zscale(Q[0], o.s0);
+            acc = zadd(acc, zscale(Q[1], zadd(o.s1, zadd(m.s0, p.s0))));
+            acc = zadd(acc, zscale(Q[2], zadd(o.s2, zadd(m.s1, p.s1))));
+            acc = zadd(acc, zscale(Q[3], zadd(m.s2, p.s2)));
         }
-        TO o;
-        o.re = acc.r;
-        o.im = acc.i;
-        y[i] = o;
+        TO v;
+        v.re = acc.r;
+        v.im = acc.i;
+        y[(long long)z * L.sy + o0] = v;
+    };
+    // window of plane sums: m (z - 1), o (z), p (z + 1); output plane z after plane z + 1 is summed
+    Raw ra, rb;
+    issue(z0 - 1, ra);
+    issue(z0, rb);
+    QSums<R> m = sums(z0 - 1, ra);
+    issue(z0 + 1, ra);
+    QSums<R> o = sums(z0, rb);
+    for (int z = z0; z < z1; z += 2) {
+        issue(z + 2, rb);
+        const QSums<R> p = sums(z + 1, ra);   // plane z + 1 (issued one step earlier)
+        emit(z, m, o, p);
+        m = o;
+        o = p;
+        if (z + 1 >= z1) break;
+        issue(z + 3, ra);
+        const QSums<R> p2 = sums(z + 2, rb);
+        emit(z + 1, m, o, p2);
+        m = o;
+        o = p2;
     }
 }
 
