@@ -121,7 +121,10 @@ typedef struct {
                                  (1..8; 0 = 1): every kernel of the solve runs once for all of them
                                  (the slot is the grid's y index), each with its own vectors and Krylov
                                  states; the workspace grows by one solver copy per slot and lane.
-                                 Results equal those of solving each right-hand side alone. */
+                                 Results equal, bit for bit, those of solving each right-hand side
+                                 alone with the same stencil tiling (setup times the tiling with all
+                                 slots running, so a batch may get other z depths than batch 1, and
+                                 the fused norms then round in another order). */
 } helm_options;
 
 /* Fill *opt with the defaults above (table NULL, stream NULL, FP32, pml_variant 0, lanes 1,
