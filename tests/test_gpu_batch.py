@@ -81,3 +81,25 @@ def test_batched_solutions_match_oracle(medium):
         print(f"\nslot {k}: |u - u_ref| / |u_ref| = {err:.2e} ({int(its[k])} calls)")
         assert err <= 1e-5, (k, err)
     o.close()
+
+
+def test_tuned_batch_tiling_matches_fixed_tiling(medium):
+    """A batch whose stencil tiling setup times with all its slots running (the default)
+    against the fixed tiling of the tests above: the same solutions up to the rounding
+    order of the fused norms (the converged-solution bar)."""
+    from paper_2608_22946_amd import helm
+    vel, omega = medium
+    f = torch.from_numpy(_sources(np.complex64)).cuda()
+    fixed = _hier(vel, omega, "fp32", batch=4)
+    tuned = helm.Hierarchy(torch.from_numpy(vel), H, omega, NPML, precision="fp32", table=load_iofd_table(),
+                           device="cuda:0", batch=4)
+    uf, itf, relf, rcf = fixed.solve(f, 1e-6)
+    ut, itt, relt, rct = tuned.solve(f, 1e-6)
+    assert rcf == 0 and rct == 0 and np.all(relt <= 1e-6)
+    for k, sp in enumerate(SOURCES):
+        if sp is None:
+            assert float(ut[k].abs().max()) == 0.0
+            continue
+        err = rel(to_np(ut[k]), to_np(uf[k]))
+        print(f"\nslot {k}: tuned vs fixed tiling {err:.2e} ({int(itt[k])} / {int(itf[k])} calls)")
+        assert err <= 1e-5, (k, err)
