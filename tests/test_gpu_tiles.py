@@ -77,3 +77,8 @@ def test_tiles_saved_and_loaded_across_processes(tmp_path):
     assert res["loaded"] >= 6 and res["calls"] == int(its)
     assert res["setup_s"] < 0.5 * res["setup_fresh_s"]
     assert np.array_equal(np.load(out), u.cpu().numpy())
+    # choices recorded for another GPU architecture are read but not used
+    arch = lines[1].split()[0]
+    foreign = tmp_path / "foreign.txt"
+    foreign.write_text(lines[0] + "\n" + " ".join(["gfx_other"] + lines[1].split()[1:]) + "\n")
+    assert arch != "gfx_other" and helm.tiles_load(str(foreign)) == 0
